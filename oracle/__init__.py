@@ -1,0 +1,123 @@
+"""FP64 CPU oracle for the explicit step of the normalised chemotaxis system.
+
+TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the CPU-baseline
+leg of the benchmark are its only users.  The product library never imports,
+links or calls anything here, and nothing here imports the product package.
+
+Contents
+  step / run / diag   plain C loops (kc_oracle.c), driven through ctypes;
+                      eqs. eqnadim / eqbadim of Sec. 2.4 with no-flux
+                      boundaries (eq. bconds), forward Euler.
+  cbar, bstar         closed-form speed bound of Sec. 4.1 (eqs. c-bar-chi0,
+                      c-bar-0) -- see cbar.py.
+  fit_velocity        least-squares slope of an envelope-radius series.
+  mlp_ref             FP64 forward / backward of the velocity surrogate MLP.
+"""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "kc_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "libkc_oracle.so")
+_lib = None
+
+CHI_RECEPTOR = 0
+CHI_CONSTANT = 1
+
+
+def build(force=False):
+    """Compile kc_oracle.c with gcc (-O3, OpenMP, no FMA contraction)."""
+    if not force and os.path.exists(_LIB_PATH) and \
+            os.path.getmtime(_LIB_PATH) >= os.path.getmtime(_SRC):
+        return _LIB_PATH
+    tmp = _LIB_PATH + ".tmp%d" % os.getpid()
+    cmd = ["gcc", "-O3", "-fopenmp", "-ffp-contract=off", "-fPIC", "-shared",
+           "-std=c99", "-o", tmp, _SRC, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        build()
+        lib = ctypes.CDLL(_LIB_PATH)
+        dp = ctypes.POINTER(ctypes.c_double)
+        lib.oracle_step.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                    ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                    ctypes.c_double, ctypes.c_int, dp, dp, dp, dp, dp]
+        lib.oracle_step.restype = None
+        lib.oracle_run.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                   ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                   ctypes.c_double, ctypes.c_int, dp, dp, dp, ctypes.c_long]
+        lib.oracle_run.restype = ctypes.c_int
+        lib.oracle_diag.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, dp, dp,
+                                    ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                    dp, dp, dp]
+        lib.oracle_diag.restype = None
+        lib.oracle_threads.argtypes = []
+        lib.oracle_threads.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _params(p):
+    return (float(p.get("D_n", 1.0)), float(p.get("theta", 1.0)), float(p.get("kappa", 1.0)),
+            float(p.get("chi", 0.0)), int(p.get("chi_law", CHI_RECEPTOR)))
+
+
+def step(b, n, sigma, h, dt, **p):
+    """One forward-Euler step; returns new (b, n) as float64 arrays [ny, nx]."""
+    lib = _load()
+    b, n, sigma = _f64(b), _f64(n), _f64(sigma)
+    ny, nx = b.shape
+    bo, no = np.empty_like(b), np.empty_like(n)
+    lib.oracle_step(nx, ny, float(h), float(dt), *_params(p),
+                    _ptr(b), _ptr(n), _ptr(sigma), _ptr(bo), _ptr(no))
+    return bo, no
+
+
+def run(b, n, sigma, h, dt, nsteps, **p):
+    """nsteps forward-Euler steps; returns (b, n) as new float64 arrays."""
+    lib = _load()
+    b, n, sigma = _f64(b).copy(), _f64(n).copy(), _f64(sigma)
+    ny, nx = b.shape
+    rc = lib.oracle_run(nx, ny, float(h), float(dt), *_params(p),
+                        _ptr(b), _ptr(n), _ptr(sigma), int(nsteps))
+    if rc != 0:
+        raise MemoryError("oracle_run: out of memory")
+    return b, n
+
+
+def diag(b, n, h, b_thr, cx=None, cy=None):
+    """(mass, nutrient, envelope radius) of one level; centre defaults to the grid centre."""
+    lib = _load()
+    b, n = _f64(b), _f64(n)
+    ny, nx = b.shape
+    cx = (nx - 1) / 2.0 if cx is None else float(cx)
+    cy = (ny - 1) / 2.0 if cy is None else float(cy)
+    m, nu, r = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    lib.oracle_diag(nx, ny, float(h), _ptr(b), _ptr(n), float(b_thr), cx, cy,
+                    ctypes.byref(m), ctypes.byref(nu), ctypes.byref(r))
+    return m.value, nu.value, r.value
+
+
+def threads():
+    """OpenMP threads the oracle step uses."""
+    return int(_load().oracle_threads())
+
+
+from .cbar import bstar, cbar, psi  # noqa: E402,F401
+from .velocity import fit_velocity  # noqa: E402,F401

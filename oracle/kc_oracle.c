@@ -1,0 +1,183 @@
+/*
+ * kc_oracle.c -- plain FP64 CPU oracle for the explicit time step of the
+ * normalised nutrient / bacteria chemotaxis system.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path links, loads or
+ * calls this file; only the test suite, the smoke check and the CPU-baseline
+ * leg of the benchmark do.  It shares no code, header or constant with the
+ * HIP library.
+ *
+ * What it computes (Leyva, Malaga, Plaza, arXiv:1301.5058):
+ *
+ *   n_t = D_n Lap(n) - kappa n b                                 (Sec. 2.4, eq. eqnadim;
+ *                                                                 D_n, kappa from eq. nutriente-dim)
+ *   b_t = div(sigma n b grad b) + theta kappa n b
+ *         - chi div( sigma n b^2 chihat(n) grad n )              (Sec. 2.4, eq. eqbadim)
+ *
+ *   chihat(n) = 1/(1+n)^2   receptor law after normalisation     (Sec. 2.2 eq. receptor_law, Sec. 2.4)
+ *   chihat(n) = 1           constant sensitivity                 (Sec. 4.1 eq. velo-system)
+ *   no-flux boundaries                                            (Sec. 2.4 eq. bconds)
+ *
+ * The normalised system has D_n = theta = kappa = 1; they are kept as
+ * parameters so that special cases (theta = 0: pure transport of b;
+ * kappa = D_n = 0: frozen nutrient) can be exercised.
+ *
+ * Discretisation (the paper only says "explicit scheme and finite
+ * differences", Sec. 3; the reading taken here):
+ *   - nx * ny cell-centred finite volumes of width h, row-major, x fastest.
+ *   - every boundary face carries zero flux (eq. bconds).
+ *   - face diffusivity: arithmetic mean of the two cell values of
+ *     D = sigma n b (eq. CoefCrsDif).
+ *   - face chemotactic coefficient X = sigma n b^2 chihat(n) (eq. chemflux)
+ *     taken from the donor cell: the bacteria move up the nutrient gradient,
+ *     so across a face with n_Q > n_P the donor is P, otherwise Q.
+ *   - forward Euler in time; every right-hand side uses the old level.
+ *
+ * All arithmetic is IEEE double, written term by term in the order of the
+ * equations above; the file is compiled without FMA contraction.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+
+#define OR_CHI_RECEPTOR 0
+#define OR_CHI_CONSTANT 1
+
+/* chihat(n): the normalised sensitivity (receptor law with K_d = 1, or 1). */
+static double chihat(double n, int chi_law)
+{
+    if (chi_law == OR_CHI_CONSTANT)
+        return 1.0;
+    return 1.0 / ((1.0 + n) * (1.0 + n));
+}
+
+/*
+ * One forward-Euler step.  b, n, sigma: input level (nx*ny each).
+ * b_out, n_out: new level (must not alias the inputs).
+ */
+void oracle_step(int nx, int ny, double h, double dt,
+                 double D_n, double theta, double kappa, double chi, int chi_law,
+                 const double *b, const double *n, const double *sigma,
+                 double *b_out, double *n_out)
+{
+    const double lam = dt / (h * h);
+    /* neighbour offsets: east, west, north (j+1), south (j-1) */
+    const int di[4] = {+1, -1, 0, 0};
+    const int dj[4] = {0, 0, +1, -1};
+
+#pragma omp parallel for schedule(static)
+    for (int j = 0; j < ny; ++j) {
+        for (int i = 0; i < nx; ++i) {
+            const long p = (long)j * nx + i;
+            const double bP = b[p], nP = n[p], sP = sigma[p];
+            /* eq. CoefCrsDif: D = sigma n b */
+            const double DP = sP * nP * bP;
+            /* eq. chemflux (normalised): X = sigma n b^2 chihat(n) */
+            const double XP = sP * nP * bP * bP * chihat(nP, chi_law);
+
+            double Fb = 0.0; /* sum over faces of (flux into P) * h^2 for b */
+            double Fn = 0.0; /* same for the nutrient Laplacian          */
+            for (int k = 0; k < 4; ++k) {
+                const int qi = i + di[k], qj = j + dj[k];
+                if (qi < 0 || qi >= nx || qj < 0 || qj >= ny)
+                    continue; /* boundary face: no flux (eq. bconds) */
+                const long q = (long)qj * nx + qi;
+                const double bQ = b[q], nQ = n[q], sQ = sigma[q];
+                const double DQ = sQ * nQ * bQ;
+                const double XQ = sQ * nQ * bQ * bQ * chihat(nQ, chi_law);
+                /* donor cell for the chemotactic flux */
+                const double Xup = (nQ > nP) ? XP : XQ;
+                const double Dface = 0.5 * (DP + DQ);
+                Fb += Dface * (bQ - bP) - chi * Xup * (nQ - nP);
+                Fn += nQ - nP;
+            }
+            /* linear kinetics f = kappa n b (eq. goodkinetics) */
+            const double r = kappa * nP * bP;
+            b_out[p] = bP + lam * Fb + dt * theta * r;
+            n_out[p] = nP + lam * D_n * Fn - dt * r;
+        }
+    }
+}
+
+/*
+ * nsteps forward-Euler steps in place on (b, n).  Returns 0, or -5 when the
+ * scratch level cannot be allocated.
+ */
+int oracle_run(int nx, int ny, double h, double dt,
+               double D_n, double theta, double kappa, double chi, int chi_law,
+               double *b, double *n, const double *sigma, long nsteps)
+{
+    const size_t cells = (size_t)nx * (size_t)ny;
+    double *b2 = (double *)malloc(cells * sizeof(double));
+    double *n2 = (double *)malloc(cells * sizeof(double));
+    if (!b2 || !n2) {
+        free(b2);
+        free(n2);
+        return -5;
+    }
+    double *bc = b, *nc = n, *bn = b2, *nn = n2;
+    for (long s = 0; s < nsteps; ++s) {
+        oracle_step(nx, ny, h, dt, D_n, theta, kappa, chi, chi_law, bc, nc, sigma, bn, nn);
+        double *t;
+        t = bc; bc = bn; bn = t;
+        t = nc; nc = nn; nn = t;
+    }
+    if (bc != b) {
+        for (size_t p = 0; p < cells; ++p) {
+            b[p] = bc[p];
+            n[p] = nc[p];
+        }
+    }
+    free(b2);
+    free(n2);
+    return 0;
+}
+
+/*
+ * Diagnostics of one level:
+ *   mass     = h^2 * sum b     (summed in row order)
+ *   nutrient = h^2 * sum n
+ *   radius   = h * max over cells with b >= b_thr of the distance of the
+ *              cell index (i, j) from (cx, cy); 0 when no cell qualifies.
+ * The paper tracks the front of b near a fixed level (Sec. 4.2); the
+ * two-dimensional envelope radius used here is that idea on the grid.
+ */
+void oracle_diag(int nx, int ny, double h, const double *b, const double *n,
+                 double b_thr, double cx, double cy,
+                 double *mass, double *nutrient, double *radius)
+{
+    double sb = 0.0, sn = 0.0, rmax = 0.0;
+    for (int j = 0; j < ny; ++j) {
+        for (int i = 0; i < nx; ++i) {
+            const long p = (long)j * nx + i;
+            sb += b[p];
+            sn += n[p];
+            if (b[p] >= b_thr) {
+                const double dx = (double)i - cx, dy = (double)j - cy;
+                const double d = sqrt(dx * dx + dy * dy);
+                if (d > rmax)
+                    rmax = d;
+            }
+        }
+    }
+    *mass = h * h * sb;
+    *nutrient = h * h * sn;
+    *radius = h * rmax;
+}
+
+/* Number of OpenMP threads oracle_step runs with (1 without OpenMP). */
+int oracle_threads(void)
+{
+    int t = 1;
+#pragma omp parallel
+    {
+#pragma omp single
+        {
+#ifdef _OPENMP
+            extern int omp_get_num_threads(void);
+            t = omp_get_num_threads();
+#endif
+        }
+    }
+    return t;
+}

@@ -1,0 +1,64 @@
+"""Seeded synthetic inputs shared by the HIP path, the tests and the benchmark.
+
+This module holds input recipes only -- none of the time step's arithmetic --
+so that the library and the CPU oracle can be fed identical data without
+sharing any code with each other.
+
+Recipe (the paper's set-up, Sec. 3, with the readings listed below):
+  * nutrient      n0 uniform over the grid (eq. inicond);
+  * bacteria      a centred Gaussian inoculum b_max exp(-d^2 / r0^2), d the
+                  distance in cells from ((nx-1)/2, (ny-1)/2) (the paper uses
+                  b_M exp(-(x^2+y^2)/6.25), eq. inibacexp), set to zero beyond
+                  cut * r0 so that no denormal tail is seeded;
+  * agar field    sigma = sigma0 (1 + a U), U ~ Uniform[-1, 1] i.i.d. per cell
+                  from numpy's default_rng(seed) (the paper perturbs sigma0 by a
+                  random Delta, Sec. 3; here the field is static per run and
+                  its amplitude a is a parameter);
+  * time step     dt = 0.2 h^2 / max(D_n, max sigma n b), rounded to FP32 so that
+                  single- and double-precision runs use the same number.
+Fields are generated in FP64 and rounded to FP32; both sides use the rounded
+values.
+"""
+import numpy as np
+
+
+def fields(nx, ny, n0, a, seed, b_max=0.7, r0=6.0, cut=3.0, sigma0=1.0):
+    """Return (b0, n0_field, sigma) as float32 arrays of shape [ny, nx]."""
+    j, i = np.meshgrid(np.arange(ny, dtype=np.float64), np.arange(nx, dtype=np.float64),
+                       indexing="ij")
+    d2 = (i - (nx - 1) / 2.0) ** 2 + (j - (ny - 1) / 2.0) ** 2
+    b = b_max * np.exp(-d2 / (r0 * r0))
+    b[d2 > (cut * r0) ** 2] = 0.0
+    n = np.full((ny, nx), float(n0))
+    u = np.random.default_rng(seed).uniform(-1.0, 1.0, (ny, nx))
+    s = sigma0 * (1.0 + a * u)
+    return b.astype(np.float32), n.astype(np.float32), s.astype(np.float32)
+
+
+def config_dt(b, n, sigma, h=1.0, D_n=1.0, factor=0.2):
+    """dt = factor h^2 / max(D_n, max sigma n b) on the given fields, FP32-rounded."""
+    m = float(np.max(np.asarray(sigma, np.float64) * np.asarray(n, np.float64)
+                     * np.asarray(b, np.float64)))
+    return float(np.float32(factor * h * h / max(D_n, m)))
+
+
+# The parameter sets of the workloads (normalised units, h = 1, D_n = theta = kappa = 1,
+# receptor-law sensitivity, envelope threshold b_thr = 0.5 n0).
+SMALL_128 = dict(nx=128, ny=128, n0=0.8, a=0.5, seed=0, chi=0.5, steps=2000)
+SINGLE_4096 = dict(nx=4096, ny=4096, n0=0.5, a=0.5, seed=0, chi=1.0, steps=50000, warmup=1000)
+HIRES_16384 = dict(nx=16384, ny=16384, n0=0.35, a=0.5, seed=0, chi=2.0, steps=20000)
+CROP_512 = dict(nx=512, ny=512, n0=0.35, a=0.5, seed=0, chi=2.0, steps=20000)
+
+
+def sweep(count=256, meta_seed=2026, sides=(256, 512, 1024, 2048)):
+    """Instance list of a parameter sweep: side ~ U{sides}, n0 ~ U[0.3, 1.2],
+    chi ~ U[0, 2], a ~ U[0.1, 0.5], sigma seed = instance index."""
+    rng = np.random.default_rng(meta_seed)
+    out = []
+    for k in range(count):
+        side = int(sides[rng.integers(0, len(sides))])
+        n0 = float(rng.uniform(0.3, 1.2))
+        chi = float(rng.uniform(0.0, 2.0))
+        a = float(rng.uniform(0.1, 0.5))
+        out.append(dict(nx=side, ny=side, n0=n0, chi=chi, a=a, seed=k))
+    return out

@@ -1,0 +1,389 @@
+"""Pins of the FP64 oracle against facts fixed by the paper and by mathematics.
+
+Each test ties the oracle to something other than itself:
+  * an exact discrete closed form (Fourier mode of the nutrient equation),
+  * exact discrete invariants (mass with theta = 0, b + n with theta = 1,
+    eq. mass-conser of Sec. 4.1),
+  * the PDE itself (eqs. eqnadim / eqbadim, Sec. 2.4) differentiated
+    symbolically,
+  * the Barenblatt solution of the porous-medium equation that the b-equation
+    becomes with frozen nutrient,
+  * brute force in exact rational arithmetic on tiny grids (a matrix
+    formulation independent of the oracle's loops),
+  * symmetries (D4 with a uniform agar field; y-invariance = the 1-D system
+    of Sec. 4.2).
+"""
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1301_5058_amd import workload
+
+pytestmark = pytest.mark.filterwarnings("ignore::DeprecationWarning")
+
+
+# ----------------------------------------------------------------------------
+# Nutrient operator and no-flux boundary: exact discrete Fourier-mode decay
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("nx,ny,kx,ky,h,D_n", [(32, 24, 3, 5, 0.7, 1.3), (17, 40, 0, 7, 1.0, 1.0),
+                                                (20, 20, 4, 0, 0.5, 0.8)])
+def test_fourier_mode_decays_at_exact_discrete_rate(nx, ny, kx, ky, h, D_n):
+    # With b = 0 the nutrient obeys n_t = D_n Lap(n) (eq. eqnadim).  The
+    # cell-centred Laplacian with no-flux faces has the cosine modes as exact
+    # eigenvectors, so forward Euler multiplies the mode by
+    # g = 1 - 4 lam D_n (sin^2(pi kx / 2 nx) + sin^2(pi ky / 2 ny)) per step.
+    dt = 0.2 * h * h / D_n
+    i = np.arange(nx) + 0.5
+    j = np.arange(ny) + 0.5
+    mode = np.cos(np.pi * ky * j / ny)[:, None] * np.cos(np.pi * kx * i / nx)[None, :]
+    nbar, A = 0.9, 0.25
+    n0 = nbar + A * mode
+    b0 = np.zeros((ny, nx))
+    sig = 1.0 + 0.5 * np.random.default_rng(1).uniform(-1, 1, (ny, nx))
+    steps = 500
+    b, n = oracle.run(b0, n0, sig, h, dt, steps, D_n=D_n, chi=0.7)
+    g = 1.0 - 4.0 * dt * D_n / h ** 2 * (np.sin(np.pi * kx / (2 * nx)) ** 2 +
+                                         np.sin(np.pi * ky / (2 * ny)) ** 2)
+    exact = nbar + A * g ** steps * mode
+    assert np.max(np.abs(n - exact)) <= 1e-13
+    assert np.all(b == 0.0)
+
+
+def test_fourier_rate_tends_to_continuum_rate():
+    # The discrete per-unit-time decay tends to exp(-D_n pi^2 (kx^2/Lx^2 + ky^2/Ly^2) t)
+    # of the PDE as h -> 0 (checks the 1/h^2 scaling of the stencil).
+    Lx, Ly, kx, ky, D_n, T = 8.0, 6.0, 2, 1, 1.0, 1.0
+    errs = []
+    for nx in (16, 32, 64):
+        h = Lx / nx
+        ny = int(round(Ly / h))
+        dt = 0.1 * h * h
+        steps = int(round(T / dt))
+        i = np.arange(nx) + 0.5
+        j = np.arange(ny) + 0.5
+        mode = np.cos(np.pi * ky * j / ny)[:, None] * np.cos(np.pi * kx * i / nx)[None, :]
+        _, n = oracle.run(np.zeros((ny, nx)), 1.0 + 0.1 * mode, np.ones((ny, nx)), h, dt, steps,
+                          D_n=D_n)
+        amp = np.sum((n - 1.0) * mode) / np.sum(mode * mode) / 0.1
+        exact = math.exp(-D_n * math.pi ** 2 * (kx ** 2 / Lx ** 2 + ky ** 2 / Ly ** 2) * steps * dt)
+        errs.append(abs(amp - exact))
+    assert errs[2] < errs[1] < errs[0]
+    assert errs[2] < 2e-4
+
+
+# ----------------------------------------------------------------------------
+# Flux form: exact discrete conservation
+# ----------------------------------------------------------------------------
+def _small_fields(nx=40, ny=48, n0=0.8, a=0.5, seed=3):
+    return workload.fields(nx, ny, n0, a, seed)
+
+
+def test_bacteria_mass_conserved_without_growth():
+    b0, n0, s = _small_fields()
+    dt = workload.config_dt(b0, n0, s)
+    b, n = oracle.run(b0, n0, s, 1.0, dt, 2000, theta=0.0, chi=0.5)
+    m0 = np.sum(b0.astype(np.float64))
+    assert abs(np.sum(b) - m0) / m0 <= 1e-13
+    # the nutrient is still consumed
+    assert np.sum(n) < np.sum(n0.astype(np.float64))
+
+
+def test_total_b_plus_n_conserved_with_unit_conversion():
+    # theta = 1: the reaction terms cancel in b + n and the fluxes telescope,
+    # the discrete form of n + b = C (eq. mass-conser).
+    b0, n0, s = _small_fields()
+    dt = workload.config_dt(b0, n0, s, D_n=1.7)
+    b, n = oracle.run(b0, n0, s, 1.0, dt, 2000, theta=1.0, chi=0.5, D_n=1.7)
+    tot0 = np.sum(b0.astype(np.float64)) + np.sum(n0.astype(np.float64))
+    assert abs(np.sum(b) + np.sum(n) - tot0) / tot0 <= 1e-13
+
+
+def test_positivity_and_monotone_nutrient_on_small_workload():
+    c = workload.SMALL_128
+    b, n, s = workload.fields(c["nx"], c["ny"], c["n0"], c["a"], c["seed"])
+    dt = workload.config_dt(b, n, s)
+    assert dt == pytest.approx(0.2, rel=1e-7)
+    nmax = float(np.max(n))
+    b, n = b.astype(np.float64), n.astype(np.float64)
+    prev_sum = np.sum(n)
+    for k in range(c["steps"]):
+        b, n = oracle.step(b, n, s, 1.0, dt, chi=c["chi"])
+        if k % 50 == 49:
+            assert np.min(b) >= 0.0
+            assert np.max(n) <= nmax
+            assert np.sum(n) <= prev_sum
+            prev_sum = np.sum(n)
+    assert np.min(b) >= 0.0 and np.min(n) >= 0.0
+
+
+# ----------------------------------------------------------------------------
+# Symmetries
+# ----------------------------------------------------------------------------
+def test_d4_symmetry_with_uniform_agar():
+    b0, n0, _ = workload.fields(64, 64, 0.8, 0.0, 0)
+    s = np.ones_like(b0)
+    b, n = oracle.run(b0, n0, s, 1.0, 0.2, 400, chi=2.0)
+    sc = np.max(b)
+    for f in (lambda a: a.T, lambda a: a[:, ::-1], lambda a: a[::-1, :]):
+        assert np.max(np.abs(b - f(b))) <= 1e-13 * sc
+        assert np.max(np.abs(n - f(n))) <= 1e-13
+
+
+def test_y_invariant_data_stays_exactly_y_invariant_and_equals_1d_run():
+    # Data depending on x only reduce the system to the 1-D system of Sec. 4.2
+    # (eq. velo-system-1d); the 2-D run must keep every row identical and equal
+    # to the run on a single row.
+    nx = 80
+    x = np.arange(nx)
+    b1 = 0.7 * np.exp(-((x - 10.0) ** 2) / 36.0)
+    n1 = 0.8 + 0.05 * np.cos(x / 7.0)
+    s1 = 1.0 + 0.4 * np.random.default_rng(5).uniform(-1, 1, nx)
+    for law in (oracle.CHI_RECEPTOR, oracle.CHI_CONSTANT):
+        b2, n2 = oracle.run(np.tile(b1, (7, 1)), np.tile(n1, (7, 1)), np.tile(s1, (7, 1)),
+                            1.0, 0.15, 300, chi=1.5, chi_law=law)
+        bb, nn = oracle.run(b1[None, :], n1[None, :], s1[None, :], 1.0, 0.15, 300, chi=1.5,
+                            chi_law=law)
+        assert np.all(b2 == bb) and np.all(n2 == nn)
+
+
+# ----------------------------------------------------------------------------
+# Whole step: exact rational brute force on tiny grids
+# ----------------------------------------------------------------------------
+def _exact_step(b, n, s, nx, ny, h, dt, D_n, theta, kappa, chi, law):
+    """Exact step written as face-incidence matrices: with G the oriented
+    face/cell incidence (G[f, first] = -1, G[f, second] = +1),
+      b' = b - lam G^T diag(Dbar_f) G b + lam chi G^T diag(X_up,f) G n + dt theta kappa n.b
+      n' = n - lam D_n G^T G n - dt kappa n.b
+    with Dbar_f the mean of D = s n b over the two cells and X_up,f the
+    X = s n b^2 chihat(n) of the cell the nutrient gradient points away from."""
+    N = nx * ny
+    faces = []
+    for j in range(ny):
+        for i in range(nx):
+            c = j * nx + i
+            if i + 1 < nx:
+                faces.append((c, c + 1))
+            if j + 1 < ny:
+                faces.append((c, c + nx))
+    F = len(faces)
+    G = [[0] * N for _ in range(F)]
+    for f, (p, q) in enumerate(faces):
+        G[f][p], G[f][q] = -1, 1
+
+    def matvec(M, v):
+        return [sum(M[r][c] * v[c] for c in range(len(v)) if M[r][c]) for r in range(len(M))]
+
+    def rmatvec(M, w):  # M^T w
+        out = [Fraction(0)] * N
+        for r in range(len(M)):
+            for c in range(N):
+                if M[r][c]:
+                    out[c] += M[r][c] * w[r]
+        return out
+
+    chihat = (lambda v: 1 / ((1 + v) * (1 + v))) if law == 0 else (lambda v: Fraction(1))
+    D = [s[c] * n[c] * b[c] for c in range(N)]
+    X = [s[c] * n[c] * b[c] * b[c] * chihat(n[c]) for c in range(N)]
+    Gb, Gn = matvec(G, b), matvec(G, n)
+    Dbar = [(D[p] + D[q]) / 2 for (p, q) in faces]
+    Xup = [X[p] if Gn[f] > 0 else X[q] for f, (p, q) in enumerate(faces)]
+    lam = dt / (h * h)
+    diff = rmatvec(G, [Dbar[f] * Gb[f] for f in range(F)])
+    chem = rmatvec(G, [Xup[f] * Gn[f] for f in range(F)])
+    lapn = rmatvec(G, Gn)
+    bn = [b[c] - lam * diff[c] + lam * chi * chem[c] + dt * theta * kappa * n[c] * b[c]
+          for c in range(N)]
+    nn = [n[c] - lam * D_n * lapn[c] - dt * kappa * n[c] * b[c] for c in range(N)]
+    return bn, nn
+
+
+@pytest.mark.parametrize("nx,ny,law,seed", [(8, 8, 0, 0), (8, 6, 0, 1), (6, 8, 1, 2), (7, 5, 0, 3)])
+def test_two_steps_match_exact_rational_brute_force(nx, ny, law, seed):
+    rng = np.random.default_rng(seed)
+    b = rng.uniform(0.05, 0.8, (ny, nx)).astype(np.float32).astype(np.float64)
+    n = rng.uniform(0.2, 1.2, (ny, nx)).astype(np.float32).astype(np.float64)
+    s = rng.uniform(0.5, 1.5, (ny, nx)).astype(np.float32).astype(np.float64)
+    b[0, 0] = 0.0  # a degenerate cell
+    h, dt, D_n, theta, kappa, chi = 0.5, 0.03125, 1.25, 0.75, 1.5, 0.625
+    bx = [Fraction(v) for v in b.ravel()]
+    nx_ = [Fraction(v) for v in n.ravel()]
+    sx = [Fraction(v) for v in s.ravel()]
+    ob, on = b, n
+    for _ in range(2):
+        bx, nx_ = _exact_step(bx, nx_, sx, nx, ny, Fraction(h), Fraction(dt), Fraction(D_n),
+                              Fraction(theta), Fraction(kappa), Fraction(chi), law)
+        ob, on = oracle.step(ob, on, s, h, dt, D_n=D_n, theta=theta, kappa=kappa, chi=chi,
+                             chi_law=law)
+    eb = np.array([float(v) for v in bx]).reshape(ny, nx)
+    en = np.array([float(v) for v in nx_]).reshape(ny, nx)
+    scale = max(np.max(np.abs(eb)), np.max(np.abs(en)))
+    assert np.max(np.abs(ob - eb)) <= 1e-14 * scale
+    assert np.max(np.abs(on - en)) <= 1e-14 * scale
+
+
+# ----------------------------------------------------------------------------
+# Consistency with the PDE of Sec. 2.4 (symbolic right-hand side)
+# ----------------------------------------------------------------------------
+def _pde_rhs(chi, law, D_n, theta, kappa):
+    import sympy as sp
+    x, y = sp.symbols("x y", real=True)
+    b = sp.Rational(2, 5) + sp.Rational(3, 20) * sp.sin(sp.Rational(7, 10) * x + sp.Rational(3, 10)) \
+        * sp.cos(sp.Rational(1, 2) * y)
+    n = sp.Rational(4, 5) + sp.Rational(1, 5) * sp.cos(sp.Rational(3, 5) * x) \
+        * sp.sin(sp.Rational(2, 5) * y + sp.Rational(1, 5))
+    s = 1 + sp.Rational(3, 10) * sp.sin(sp.Rational(9, 10) * x + sp.Rational(2, 5) * y)
+    chih = 1 / (1 + n) ** 2 if law == 0 else sp.Integer(1)
+
+    def div(fx, fy):
+        return sp.diff(fx, x) + sp.diff(fy, y)
+
+    Db = s * n * b
+    Xc = s * n * b ** 2 * chih
+    rb = div(Db * sp.diff(b, x), Db * sp.diff(b, y)) + theta * kappa * n * b \
+        - chi * div(Xc * sp.diff(n, x), Xc * sp.diff(n, y))
+    rn = D_n * div(sp.diff(n, x), sp.diff(n, y)) - kappa * n * b
+    f = [sp.lambdify((x, y), e, "numpy") for e in (b, n, s, rb, rn)]
+    return f
+
+
+@pytest.mark.parametrize("law", [0, 1])
+def test_one_step_increment_converges_to_pde_right_hand_side(law):
+    chi, D_n, theta, kappa = 1.5, 1.2, 0.9, 1.1
+    fb, fn, fs, frb, frn = _pde_rhs(chi, law, D_n, theta, kappa)
+    L, errs_b, errs_n = 8.0, [], []
+    for nx in (32, 64, 128):
+        h = L / nx
+        xc = (np.arange(nx) + 0.5) * h
+        X, Y = np.meshgrid(xc, xc)
+        b, n, s = fb(X, Y), fn(X, Y), fs(X, Y)
+        dt = 1e-3 * h * h
+        b1, n1 = oracle.step(b, n, s, h, dt, D_n=D_n, theta=theta, kappa=kappa, chi=chi,
+                             chi_law=law)
+        inner = (slice(2, -2), slice(2, -2))
+        eb = np.max(np.abs((b1 - b)[inner] / dt - frb(X, Y)[inner]))
+        en = np.max(np.abs((n1 - n)[inner] / dt - frn(X, Y)[inner]))
+        errs_b.append(eb / np.max(np.abs(frb(X, Y))))
+        errs_n.append(en / np.max(np.abs(frn(X, Y))))
+    # donor-cell chemotaxis is first order, the rest second order
+    assert errs_b[1] < 0.65 * errs_b[0] and errs_b[2] < 0.65 * errs_b[1]
+    assert errs_b[2] < 0.05
+    assert errs_n[2] < 0.3 * errs_n[1] < 0.09 * errs_n[0]
+    assert errs_n[2] < 1e-3
+
+
+# ----------------------------------------------------------------------------
+# Degenerate diffusion: Barenblatt solution of b_t = k Lap(b^2)
+# ----------------------------------------------------------------------------
+def _barenblatt(r2, t, k, C):
+    kt = k * t
+    return np.maximum(C - r2 / (16.0 * math.sqrt(kt)), 0.0) / math.sqrt(kt)
+
+
+def test_frozen_nutrient_reduces_to_porous_medium_barenblatt():
+    # kappa = D_n = 0, theta = 0, sigma = 1, n = nbar: eq. eqbadim becomes
+    # b_t = div(nbar b grad b) = (nbar/2) Lap(b^2), whose source solution is
+    # b = (kt)^(-1/2) (C - |x|^2 / (16 sqrt(kt)))_+ with k = nbar/2, mass 8 pi C^2,
+    # front radius 4 sqrt(C) (kt)^(1/4).  The chemotactic term vanishes because
+    # grad n = 0 (any chi).
+    nbar, C, t0, t1, L = 2.0, 1.0, 10.0, 50.0, 32.0
+    k = nbar / 2.0
+    l1 = []
+    for nx in (32, 64, 128):
+        h = L / nx
+        xc = (np.arange(nx) + 0.5) * h - L / 2
+        X, Y = np.meshgrid(xc, xc)
+        r2 = X * X + Y * Y
+        b0 = _barenblatt(r2, t0, k, C)
+        dt = 0.2 * h * h / (nbar * b0.max())
+        steps = int(round((t1 - t0) / dt))
+        dt = (t1 - t0) / steps
+        b, n = oracle.run(b0, np.full_like(b0, nbar), np.ones_like(b0), h, dt, steps,
+                          D_n=0.0, kappa=0.0, theta=0.0, chi=3.0)
+        assert np.all(n == nbar)
+        assert abs(np.sum(b) - np.sum(b0)) <= 1e-13 * np.sum(b0)
+        ex = _barenblatt(r2, t1, k, C)
+        l1.append(np.sum(np.abs(b - ex)) * h * h / (8 * math.pi * C * C))
+        # front radius: farthest cell with b above 1e-2 of the peak
+        rf = math.sqrt(np.max(r2[b >= 1e-2 * b.max()]))
+        R_exact = 4.0 * math.sqrt(C) * (k * t1) ** 0.25 * math.sqrt(1.0 - 1e-2)
+        assert abs(rf - R_exact) <= 1.0 * h + 1e-12
+    order1 = math.log2(l1[0] / l1[1])
+    order2 = math.log2(l1[1] / l1[2])
+    assert order1 > 1.4 and order2 > 1.4
+    assert l1[2] < 3e-3
+
+
+# ----------------------------------------------------------------------------
+# Diagnostics
+# ----------------------------------------------------------------------------
+def test_diagnostics_by_hand():
+    b = np.zeros((5, 7))
+    n = np.full((5, 7), 0.5)
+    b[2, 3] = 1.0   # centre (cx, cy) = (3, 2): distance 0
+    b[4, 6] = 0.6   # distance sqrt(9 + 4)
+    b[0, 1] = 0.4   # below threshold
+    m, nu, r = oracle.diag(b, n, 0.5, 0.5)
+    assert m == pytest.approx(0.25 * 2.0, rel=1e-15)
+    assert nu == pytest.approx(0.25 * 35 * 0.5, rel=1e-15)
+    assert r == pytest.approx(0.5 * math.sqrt(13.0), rel=1e-15)
+    assert oracle.diag(np.zeros((4, 4)), n[:4, :4], 1.0, 0.1)[2] == 0.0
+
+
+# ----------------------------------------------------------------------------
+# Speed bound of Sec. 4.1 and the velocity fit
+# ----------------------------------------------------------------------------
+def _golden(name):
+    path = os.path.join(os.path.dirname(__file__), "golden", name)
+    rows = []
+    with open(path) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                rows.append([c.strip() for c in line.split("|")])
+    return rows
+
+
+def test_speed_bound_matches_printed_closed_forms():
+    for name, n0, chi, s0, val, _cite in _golden("speed_bound_sec4_1.txt"):
+        n0, chi, s0, val = float(n0), float(chi), float(s0), float(val)
+        if name == "psi_max_chi0":
+            assert oracle.psi(oracle.bstar(n0, chi), n0, chi) == pytest.approx(val, rel=1e-14)
+        elif name == "argmax_chi0":
+            assert oracle.bstar(n0, chi) == pytest.approx(val, rel=1e-14)
+        elif name == "cbar_chi0":
+            assert oracle.cbar(n0, chi, s0) == pytest.approx(val, rel=1e-14)
+    for n0 in (0.35, 0.71, 1.07, 2.0, 3.0, 4.0):
+        for s0 in (1.0, 4.0):
+            assert oracle.cbar(n0, 0.0, s0) == pytest.approx(
+                4.0 / (3.0 * math.sqrt(3.0)) * n0 ** 1.5 * math.sqrt(s0), rel=1e-14)
+
+
+@pytest.mark.parametrize("n0", [0.35, 0.71, 1.07, 2.0, 3.0, 4.0])
+def test_speed_bound_equals_brute_force_maximum_and_printed_bstar(n0):
+    bgrid = np.linspace(0.0, n0, 2_000_001)
+    prev = 0.0
+    for chi in (0.0, 1.0, 2.5, 5.0, 7.5, 10.0):
+        brute = 2.0 * n0 * math.sqrt(np.max(oracle.psi(bgrid, n0, chi)))
+        c = oracle.cbar(n0, chi)
+        assert c == pytest.approx(brute, rel=1e-9)
+        assert c >= prev  # Proposition 1(i): cbar is non-decreasing in chi0
+        prev = c
+        if chi > 0:
+            # the printed maximiser (Sec. 4.1)
+            q = n0 / 2.0 - 3.0 / (4.0 * chi)
+            printed = 0.5 * q + 0.5 * math.sqrt(q * q + n0 / chi)
+            assert oracle.bstar(n0, chi) == pytest.approx(printed, rel=1e-12)
+            assert 0.0 < oracle.bstar(n0, chi) < n0
+
+
+def test_velocity_fit_recovers_slope_inside_window():
+    t = np.arange(0, 3001, 100.0)
+    R = 5.0 + 0.0123 * t
+    R[:3] = 100.0  # outside the window: ignored
+    v, k = oracle.fit_velocity(t, R, 10.0, 40.0)
+    assert v == pytest.approx(0.0123, rel=1e-12)
+    assert k == int(np.sum((R >= 10) & (R <= 40)))
+    assert math.isnan(oracle.fit_velocity(t, R, 1e9, 2e9)[0])
