@@ -1,0 +1,146 @@
+/*
+ * kc.h -- C ABI of the MI355X (gfx950) solver for the normalised
+ * nutrient / bacteria chemotaxis system of Leyva, Malaga and Plaza,
+ * "The effects of nutrient chemotaxis on bacterial aggregation patterns with
+ * non-linear degenerate cross diffusion" (arXiv:1301.5058):
+ *
+ *   n_t = D_n Lap(n) - kappa n b                                   Sec. 2.4, eq. eqnadim
+ *   b_t = div(sigma n b grad b) + theta kappa n b
+ *         - chi div(sigma n b^2 chihat(n) grad n)                  Sec. 2.4, eq. eqbadim
+ *   chihat(n) = 1/(1+n)^2 (receptor law, eq. receptor_law with K_d = 1)
+ *             or 1        (constant sensitivity, Sec. 4.1 eq. velo-system)
+ *   no-flux boundaries                                              Sec. 2.4, eq. bconds
+ *
+ * The normalised system has D_n = theta = kappa = 1 and a free agar field
+ * sigma = sigma0 (1 + Delta) (eq. CoefCrsDif); the three rates are kept as
+ * parameters.  The paper's scheme is "explicit ... finite differences"
+ * (Sec. 3).  This library advances the system with forward Euler on nx * ny
+ * cell-centred finite volumes of width h: the face diffusivity of the b-flux
+ * is the mean of sigma n b over the two cells, the chemotactic coefficient
+ * sigma n b^2 chihat(n) is taken from the donor cell (the cell the nutrient
+ * gradient points away from), and every boundary face carries zero flux.
+ *
+ * Layout.  Fields passed in or out are dense row-major [ny][nx] arrays, x
+ * fastest, of the context's precision (float for KC_FP32, double for
+ * KC_FP64).  Host pointers (KC_MEM_HOST) are ordinary CPU memory; device
+ * pointers (KC_MEM_DEVICE) are device memory of the current HIP device.  The
+ * context keeps its own padded device copies; the caller keeps ownership of
+ * every buffer it passes, and no call retains a caller pointer.
+ *
+ * Streams.  All device work of a context is enqueued on the hipStream_t
+ * given at creation (NULL = the legacy default stream).  kc_step and
+ * kc_diagnostics_device return after enqueueing; kc_set_fields,
+ * kc_get_fields and kc_diagnostics return after the stream has drained the
+ * work they need.
+ *
+ * Errors.  Every int-returning call returns KC_OK (0) or a negative code
+ * below; a message for the last failure of a context is kept until its next
+ * call (kc_last_error).  Invalid arguments are rejected before any device
+ * work is enqueued.  A context is not thread-safe; distinct contexts are
+ * independent.
+ */
+#ifndef KC_H
+#define KC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define KC_OK 0
+#define KC_EINVAL -1     /* null pointer, nx or ny < 1, h <= 0, dt <= 0, negative rate, bad enum, size overflow */
+#define KC_ENONFINITE -2 /* NaN / Inf or negative value in b0, n0 or sigma                               */
+#define KC_EUNSTABLE -3  /* dt > h^2 / (4 max(D_n, max sigma n b)) on the fields given to kc_set_fields  */
+#define KC_ESTATE -4     /* step / diagnostics / get before kc_set_fields                                */
+#define KC_ENOMEM -5     /* device or host allocation failed                                             */
+#define KC_EHIP -6       /* no usable device, or a HIP runtime error                                     */
+
+enum { KC_FP32 = 0, KC_FP64 = 1 };
+enum { KC_CHI_RECEPTOR = 0, KC_CHI_CONSTANT = 1 };
+enum { KC_MEM_HOST = 0, KC_MEM_DEVICE = 1 };
+
+typedef struct kc_ctx kc_ctx;
+
+typedef struct {
+    int32_t nx; /* cells along x (fastest index), >= 1 */
+    int32_t ny; /* cells along y, >= 1                 */
+} kc_grid;
+
+typedef struct {
+    double D_n;        /* nutrient diffusivity (1 in the normalised system), >= 0           */
+    double theta;      /* conversion of consumed nutrient into bacteria (1), >= 0           */
+    double kappa;      /* uptake rate of f = kappa n b, eq. goodkinetics (1), >= 0         */
+    double chi;        /* chemotactic strength chi_0 >= 0 (Sec. 2.4; 0 = Kawasaki model)   */
+    int32_t chi_law;   /* KC_CHI_RECEPTOR or KC_CHI_CONSTANT                                */
+    int32_t precision; /* KC_FP32 (fields float, reductions double) or KC_FP64              */
+    double b_thr;      /* envelope threshold: cells with b >= b_thr count for the radius   */
+    double cx, cy;     /* envelope centre in cell-index units (default (nx-1)/2, (ny-1)/2) */
+    int64_t step0;     /* step count at which the given fields sit (time = steps * dt)     */
+} kc_params;
+
+/* Fill *p with the normalised defaults: D_n = theta = kappa = 1, chi = 0,
+ * receptor law, FP32, b_thr = 0.5, centre unset (NaN -> grid centre), step0 = 0. */
+void kc_default_params(kc_params *p);
+
+/* Create a context for grid g, cell width h > 0 and time step dt > 0 on the
+ * current HIP device; hip_stream is a hipStream_t or NULL.  Allocates the
+ * padded device fields.  *out receives the context (NULL on failure). */
+int kc_create(const kc_grid *g, double h, double dt, const kc_params *p, void *hip_stream,
+              kc_ctx **out);
+
+/* Copy initial fields b0 (bacteria), n0 (nutrient) and sigma (agar field,
+ * eq. CoefCrsDif) into the context; mem says where the three arrays live.
+ * Rejects NaN / Inf / negative entries (KC_ENONFINITE) and a dt above the
+ * explicit stability bound for these fields (KC_EUNSTABLE); on failure the
+ * context keeps its previous state.  Resets the step count to p->step0. */
+int kc_set_fields(kc_ctx *ctx, const void *b0, const void *n0, const void *sigma, int mem);
+
+/* Advance nsteps >= 0 forward-Euler steps (enqueued, asynchronous). */
+int kc_step(kc_ctx *ctx, int64_t nsteps);
+
+/* Diagnostics of the current level, synchronous:
+ *   mass = h^2 sum b, nutrient = h^2 sum n (both accumulated in double),
+ *   envelope_radius = h * max distance of a cell with b >= b_thr from (cx, cy)
+ *   (0 when no cell qualifies).  Any output pointer may be NULL. */
+int kc_diagnostics(kc_ctx *ctx, double *mass, double *nutrient, double *envelope_radius);
+
+/* Same diagnostics, enqueued: writes {time, mass, nutrient, envelope_radius}
+ * as 4 doubles to device memory dev_out4 when the stream reaches it. */
+int kc_diagnostics_device(kc_ctx *ctx, double *dev_out4);
+
+/* Copy the current level out (synchronous).  Either pointer may be NULL. */
+int kc_get_fields(kc_ctx *ctx, void *b, void *n, int mem);
+
+/* Current time (step count times dt, in double) and step count. */
+int kc_time(const kc_ctx *ctx, double *t, int64_t *steps);
+
+/* 0.2 h^2 / max(D_n, max_sigma_n_b): a time step with a 5x margin over the
+ * diffusive explicit limit h^2 / (4 max D). */
+double kc_suggest_dt(double h, double D_n, double max_sigma_n_b);
+
+/* Host-side check of dense host arrays (no device work): KC_OK, KC_EINVAL for
+ * null pointers or bad sizes, KC_ENONFINITE for NaN / Inf / negative entries.
+ * *max_sigma_n_b (may be NULL) receives max sigma n b over the cells. */
+int kc_check_fields(int32_t nx, int32_t ny, int precision, const void *b0, const void *n0,
+                    const void *sigma, double *max_sigma_n_b);
+
+/* Kernel configuration: tsteps = time steps fused into one launch (1..8),
+ * rows = output rows per wavefront strip (>= 1), prefetch = rows loaded ahead
+ * (2 or 4).  0 keeps the current value.  Results do not depend on it. */
+int kc_set_tuning(kc_ctx *ctx, int32_t tsteps, int32_t rows, int32_t prefetch);
+int kc_get_tuning(const kc_ctx *ctx, int32_t *tsteps, int32_t *rows, int32_t *prefetch);
+
+/* Use the one-step-per-launch global-memory kernel (1) or the fused,
+ * register-streaming kernel (0, default).  Both give bitwise equal fields. */
+int kc_set_reference_kernel(kc_ctx *ctx, int32_t on);
+
+void kc_destroy(kc_ctx *ctx);
+const char *kc_strerror(int status);
+const char *kc_last_error(const kc_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KC_H */

@@ -1,0 +1,500 @@
+// kc_api.hip -- the C ABI of include/kc.h: argument checking, device memory,
+// launch planning.  Every step of the computation runs in the kernels of
+// kc_step.hip and kc_diag.hip; this file only validates, allocates, copies and
+// enqueues.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "kc.h"
+#include "kc_internal.h"
+
+using kc::Coef;
+using kc::Fields;
+
+struct kc_ctx {
+    int nx = 0, ny = 0, pitch = 0;
+    double h = 0, dt = 0;
+    kc_params p{};
+    size_t esz = 4;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    void *b[2] = {nullptr, nullptr};
+    void *n[2] = {nullptr, nullptr};
+    void *sg = nullptr;
+    int cur = 0;
+    bool has_fields = false;
+    int64_t steps = 0;
+    kc::Tuning tune{2, 32, 4};
+    bool ref = false;
+    double *dparts = nullptr; // diagnostics partials, then out4 (4 doubles)
+    double *dout4 = nullptr;
+    double *hout = nullptr; // pinned host copy of out4
+    std::string err;
+};
+
+namespace {
+
+int fail(kc_ctx *c, int code, const char *fmt, ...)
+{
+    if (c) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        c->err = buf;
+    }
+    return code;
+}
+
+int hipfail(kc_ctx *c, hipError_t e, const char *what)
+{
+    const int code = (e == hipErrorOutOfMemory) ? KC_ENOMEM : KC_EHIP;
+    return fail(c, code, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define KC_HIP(ctx, expr)                                                                          \
+    do {                                                                                           \
+        hipError_t e_ = (expr);                                                                    \
+        if (e_ != hipSuccess)                                                                      \
+            return hipfail((ctx), e_, #expr);                                                      \
+    } while (0)
+
+bool finite_nonneg(double v) { return isfinite(v) && v >= 0.0; }
+
+int check_params(const kc_params *p)
+{
+    if (!p)
+        return KC_EINVAL;
+    if (!finite_nonneg(p->D_n) || !finite_nonneg(p->theta) || !finite_nonneg(p->kappa) ||
+        !finite_nonneg(p->chi))
+        return KC_EINVAL;
+    if (p->chi_law != KC_CHI_RECEPTOR && p->chi_law != KC_CHI_CONSTANT)
+        return KC_EINVAL;
+    if (p->precision != KC_FP32 && p->precision != KC_FP64)
+        return KC_EINVAL;
+    if (isnan(p->b_thr) || p->step0 < 0)
+        return KC_EINVAL;
+    return KC_OK;
+}
+
+// Default wavefront-strip height: about 2048 strips so the whole chip is busy.
+int default_rows(int precision, int tsteps, int nx, int ny)
+{
+    const kc::StreamGeom g = kc::stream_geom(precision, tsteps, nx, ny, 1);
+    long rows = ((long)ny * g.nsx + 2047) / 2048;
+    if (rows < 8)
+        rows = 8;
+    return (int)rows;
+}
+
+template <typename R> Coef<R> make_coef(const kc_ctx *c)
+{
+    const double lam = c->dt / (c->h * c->h);
+    Coef<R> k;
+    k.lam = (R)lam;
+    k.lamDn = (R)(lam * c->p.D_n);
+    k.gro = (R)(c->dt * c->p.theta * c->p.kappa);
+    k.upt = (R)(c->dt * c->p.kappa);
+    k.chi2 = (R)(2.0 * c->p.chi);
+    return k;
+}
+
+template <typename R> Fields<R> make_fields(const kc_ctx *c)
+{
+    Fields<R> f;
+    f.b_in = (const R *)c->b[c->cur];
+    f.n_in = (const R *)c->n[c->cur];
+    f.sg = (const R *)c->sg;
+    f.b_out = (R *)c->b[c->cur ^ 1];
+    f.n_out = (R *)c->n[c->cur ^ 1];
+    f.nx = c->nx;
+    f.ny = c->ny;
+    f.pitch = c->pitch;
+    return f;
+}
+
+template <typename R> int step_impl(kc_ctx *c, int64_t nsteps)
+{
+    const Coef<R> k = make_coef<R>(c);
+    while (nsteps > 0) {
+        const Fields<R> f = make_fields<R>(c);
+        hipError_t e;
+        int adv;
+        if (c->ref) {
+            e = kc::launch_ref<R>(f, k, c->p.chi_law, c->stream);
+            adv = 1;
+        } else {
+            kc::Tuning t = c->tune;
+            const int64_t want = nsteps < t.tsteps ? nsteps : t.tsteps;
+            t.tsteps = kc::stream_depth_at_most((int)want);
+            e = kc::launch_stream<R>(f, k, c->p.chi_law, t, c->stream);
+            adv = t.tsteps;
+        }
+        if (e != hipSuccess)
+            return hipfail(c, e, "step kernel launch");
+        c->cur ^= 1;
+        c->steps += adv;
+        nsteps -= adv;
+    }
+    return KC_OK;
+}
+
+template <typename R> int check_host(int nx, int ny, const R *b, const R *n, const R *s, double *mx)
+{
+    const size_t cells = (size_t)nx * (size_t)ny;
+    double m = 0.0;
+    for (size_t i = 0; i < cells; ++i) {
+        const double bv = b[i], nv = n[i], sv = s[i];
+        if (!(isfinite(bv) && isfinite(nv) && isfinite(sv)) || bv < 0 || nv < 0 || sv < 0)
+            return KC_ENONFINITE;
+        const double v = sv * nv * bv;
+        if (v > m)
+            m = v;
+    }
+    if (mx)
+        *mx = m;
+    return KC_OK;
+}
+
+bool sizes_ok(int nx, int ny)
+{
+    return nx >= 1 && ny >= 1 && nx <= (1 << 20) && ny <= (1 << 20) &&
+           (double)kc::pitch_for(nx) * (double)ny < 4.0e9;
+}
+
+} // namespace
+
+extern "C" {
+
+void kc_default_params(kc_params *p)
+{
+    if (!p)
+        return;
+    p->D_n = 1.0;
+    p->theta = 1.0;
+    p->kappa = 1.0;
+    p->chi = 0.0;
+    p->chi_law = KC_CHI_RECEPTOR;
+    p->precision = KC_FP32;
+    p->b_thr = 0.5;
+    p->cx = NAN;
+    p->cy = NAN;
+    p->step0 = 0;
+}
+
+const char *kc_strerror(int s)
+{
+    switch (s) {
+    case KC_OK: return "ok";
+    case KC_EINVAL: return "invalid argument";
+    case KC_ENONFINITE: return "non-finite or negative field value";
+    case KC_EUNSTABLE: return "time step above the explicit stability bound";
+    case KC_ESTATE: return "fields not set";
+    case KC_ENOMEM: return "out of memory";
+    case KC_EHIP: return "HIP runtime error";
+    default: return "unknown status";
+    }
+}
+
+const char *kc_last_error(const kc_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+double kc_suggest_dt(double h, double D_n, double max_sigma_n_b)
+{
+    const double m = D_n > max_sigma_n_b ? D_n : max_sigma_n_b;
+    if (!(h > 0) || !(m > 0))
+        return 0.0;
+    return 0.2 * h * h / m;
+}
+
+int kc_check_fields(int32_t nx, int32_t ny, int precision, const void *b0, const void *n0,
+                    const void *sigma, double *max_sigma_n_b)
+{
+    if (!b0 || !n0 || !sigma || !sizes_ok(nx, ny))
+        return KC_EINVAL;
+    if (precision == KC_FP32)
+        return check_host<float>(nx, ny, (const float *)b0, (const float *)n0,
+                                 (const float *)sigma, max_sigma_n_b);
+    if (precision == KC_FP64)
+        return check_host<double>(nx, ny, (const double *)b0, (const double *)n0,
+                                  (const double *)sigma, max_sigma_n_b);
+    return KC_EINVAL;
+}
+
+int kc_create(const kc_grid *g, double h, double dt, const kc_params *p, void *hip_stream,
+              kc_ctx **out)
+{
+    if (!out)
+        return KC_EINVAL;
+    *out = nullptr;
+    if (!g || !sizes_ok(g->nx, g->ny) || !(h > 0) || !isfinite(h) || !(dt > 0) || !isfinite(dt))
+        return KC_EINVAL;
+    if (check_params(p) != KC_OK)
+        return KC_EINVAL;
+
+    kc_ctx *c = new (std::nothrow) kc_ctx;
+    if (!c)
+        return KC_ENOMEM;
+    c->nx = g->nx;
+    c->ny = g->ny;
+    c->pitch = kc::pitch_for(g->nx);
+    c->h = h;
+    c->dt = dt;
+    c->p = *p;
+    if (isnan(c->p.cx))
+        c->p.cx = 0.5 * (c->nx - 1);
+    if (isnan(c->p.cy))
+        c->p.cy = 0.5 * (c->ny - 1);
+    c->esz = p->precision == KC_FP32 ? 4 : 8;
+    c->stream = (hipStream_t)hip_stream;
+    c->steps = p->step0;
+    c->tune.tsteps = p->precision == KC_FP32 ? 2 : 2;
+    c->tune.prefetch = 4;
+    c->tune.rows = default_rows(p->precision, c->tune.tsteps, c->nx, c->ny);
+
+    int rc = KC_OK;
+    hipError_t e = hipGetDevice(&c->device);
+    if (e != hipSuccess) {
+        delete c;
+        return KC_EHIP;
+    }
+    const size_t bytes = (size_t)c->pitch * c->ny * c->esz;
+    void **bufs[5] = {&c->b[0], &c->n[0], &c->b[1], &c->n[1], &c->sg};
+    for (void **bp : bufs) {
+        e = hipMalloc(bp, bytes);
+        if (e != hipSuccess) {
+            rc = e == hipErrorOutOfMemory ? KC_ENOMEM : KC_EHIP;
+            break;
+        }
+        e = hipMemset(*bp, 0, bytes);
+        if (e != hipSuccess) {
+            rc = KC_EHIP;
+            break;
+        }
+    }
+    if (rc == KC_OK) {
+        const int np = kc::diag_parts(c->ny);
+        const size_t cells = (size_t)c->nx * c->ny;
+        const int cp = kc::check_parts(cells);
+        const size_t nparts = (size_t)(3 * np > 2 * cp ? 3 * np : 2 * cp);
+        e = hipMalloc((void **)&c->dparts, (nparts + 4) * sizeof(double));
+        if (e != hipSuccess)
+            rc = e == hipErrorOutOfMemory ? KC_ENOMEM : KC_EHIP;
+        else
+            c->dout4 = c->dparts + nparts;
+    }
+    if (rc == KC_OK) {
+        e = hipHostMalloc((void **)&c->hout, 2 * kc::check_parts((size_t)c->nx * c->ny) *
+                                                 sizeof(double) + 4 * sizeof(double),
+                          hipHostMallocDefault);
+        if (e != hipSuccess)
+            rc = KC_ENOMEM;
+    }
+    if (rc != KC_OK) {
+        kc_destroy(c);
+        return rc;
+    }
+    *out = c;
+    return KC_OK;
+}
+
+void kc_destroy(kc_ctx *c)
+{
+    if (!c)
+        return;
+    if (c->stream || c->b[0])
+        (void)hipStreamSynchronize(c->stream);
+    for (void *q : {c->b[0], c->n[0], c->b[1], c->n[1], c->sg})
+        if (q)
+            (void)hipFree(q);
+    if (c->dparts)
+        (void)hipFree(c->dparts);
+    if (c->hout)
+        (void)hipHostFree(c->hout);
+    delete c;
+}
+
+int kc_set_fields(kc_ctx *c, const void *b0, const void *n0, const void *sigma, int mem)
+{
+    if (!c)
+        return KC_EINVAL;
+    c->err.clear();
+    if (!b0 || !n0 || !sigma)
+        return fail(c, KC_EINVAL, "null field pointer");
+    if (mem != KC_MEM_HOST && mem != KC_MEM_DEVICE)
+        return fail(c, KC_EINVAL, "bad memory kind %d", mem);
+    const size_t cells = (size_t)c->nx * c->ny;
+    double mx = 0.0;
+    if (mem == KC_MEM_HOST) {
+        const int rc = kc_check_fields(c->nx, c->ny, c->p.precision, b0, n0, sigma, &mx);
+        if (rc != KC_OK)
+            return fail(c, rc, "input fields rejected: %s", kc_strerror(rc));
+    } else {
+        const int cp = kc::check_parts(cells);
+        hipError_t e = c->p.precision == KC_FP32
+                           ? kc::launch_check<float>((const float *)b0, (const float *)n0,
+                                                     (const float *)sigma, cells, c->dparts,
+                                                     c->stream)
+                           : kc::launch_check<double>((const double *)b0, (const double *)n0,
+                                                      (const double *)sigma, cells, c->dparts,
+                                                      c->stream);
+        if (e != hipSuccess)
+            return hipfail(c, e, "input check kernel");
+        KC_HIP(c, hipMemcpyAsync(c->hout, c->dparts, 2 * cp * sizeof(double),
+                                 hipMemcpyDeviceToHost, c->stream));
+        KC_HIP(c, hipStreamSynchronize(c->stream));
+        double nbad = 0.0;
+        for (int i = 0; i < cp; ++i) {
+            nbad += c->hout[2 * i];
+            if (c->hout[2 * i + 1] > mx)
+                mx = c->hout[2 * i + 1];
+        }
+        if (nbad > 0)
+            return fail(c, KC_ENONFINITE, "input fields rejected: %.0f NaN/Inf/negative entries",
+                        nbad);
+    }
+    const double dmax = c->p.D_n > mx ? c->p.D_n : mx;
+    if (dmax > 0 && c->dt > c->h * c->h / (4.0 * dmax))
+        return fail(c, KC_EUNSTABLE, "dt = %g exceeds h^2/(4 max(D_n, sigma n b)) = %g", c->dt,
+                    c->h * c->h / (4.0 * dmax));
+
+    const hipMemcpyKind kind = mem == KC_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+    const size_t spitch = (size_t)c->nx * c->esz, dpitch = (size_t)c->pitch * c->esz;
+    c->cur = 0;
+    KC_HIP(c, hipMemcpy2DAsync(c->b[0], dpitch, b0, spitch, spitch, c->ny, kind, c->stream));
+    KC_HIP(c, hipMemcpy2DAsync(c->n[0], dpitch, n0, spitch, spitch, c->ny, kind, c->stream));
+    KC_HIP(c, hipMemcpy2DAsync(c->sg, dpitch, sigma, spitch, spitch, c->ny, kind, c->stream));
+    KC_HIP(c, hipStreamSynchronize(c->stream));
+    c->has_fields = true;
+    c->steps = c->p.step0;
+    return KC_OK;
+}
+
+int kc_step(kc_ctx *c, int64_t nsteps)
+{
+    if (!c)
+        return KC_EINVAL;
+    c->err.clear();
+    if (nsteps < 0)
+        return fail(c, KC_EINVAL, "negative step count");
+    if (!c->has_fields)
+        return fail(c, KC_ESTATE, "kc_step before kc_set_fields");
+    return c->p.precision == KC_FP32 ? step_impl<float>(c, nsteps) : step_impl<double>(c, nsteps);
+}
+
+int kc_diagnostics_device(kc_ctx *c, double *dev_out4)
+{
+    if (!c || !dev_out4)
+        return KC_EINVAL;
+    c->err.clear();
+    if (!c->has_fields)
+        return fail(c, KC_ESTATE, "diagnostics before kc_set_fields");
+    const double t = (double)c->steps * c->dt;
+    hipError_t e;
+    if (c->p.precision == KC_FP32)
+        e = kc::launch_diag<float>((const float *)c->b[c->cur], (const float *)c->n[c->cur], c->nx,
+                                   c->ny, c->pitch, c->h, t, c->p.b_thr, c->p.cx, c->p.cy,
+                                   c->dparts, dev_out4, c->stream);
+    else
+        e = kc::launch_diag<double>((const double *)c->b[c->cur], (const double *)c->n[c->cur],
+                                    c->nx, c->ny, c->pitch, c->h, t, c->p.b_thr, c->p.cx, c->p.cy,
+                                    c->dparts, dev_out4, c->stream);
+    if (e != hipSuccess)
+        return hipfail(c, e, "diagnostics launch");
+    return KC_OK;
+}
+
+int kc_diagnostics(kc_ctx *c, double *mass, double *nutrient, double *radius)
+{
+    const int rc = kc_diagnostics_device(c, c ? c->dout4 : nullptr);
+    if (rc != KC_OK)
+        return rc;
+    KC_HIP(c, hipMemcpyAsync(c->hout, c->dout4, 4 * sizeof(double), hipMemcpyDeviceToHost,
+                             c->stream));
+    KC_HIP(c, hipStreamSynchronize(c->stream));
+    if (!isfinite(c->hout[1]) || !isfinite(c->hout[2]))
+        return fail(c, KC_ENONFINITE, "non-finite mass or nutrient (mass %g, nutrient %g)",
+                    c->hout[1], c->hout[2]);
+    if (mass)
+        *mass = c->hout[1];
+    if (nutrient)
+        *nutrient = c->hout[2];
+    if (radius)
+        *radius = c->hout[3];
+    return KC_OK;
+}
+
+int kc_get_fields(kc_ctx *c, void *b, void *n, int mem)
+{
+    if (!c)
+        return KC_EINVAL;
+    c->err.clear();
+    if (mem != KC_MEM_HOST && mem != KC_MEM_DEVICE)
+        return fail(c, KC_EINVAL, "bad memory kind %d", mem);
+    if (!c->has_fields)
+        return fail(c, KC_ESTATE, "kc_get_fields before kc_set_fields");
+    const hipMemcpyKind kind = mem == KC_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
+    const size_t dpitch = (size_t)c->nx * c->esz, spitch = (size_t)c->pitch * c->esz;
+    if (b)
+        KC_HIP(c, hipMemcpy2DAsync(b, dpitch, c->b[c->cur], spitch, dpitch, c->ny, kind, c->stream));
+    if (n)
+        KC_HIP(c, hipMemcpy2DAsync(n, dpitch, c->n[c->cur], spitch, dpitch, c->ny, kind, c->stream));
+    KC_HIP(c, hipStreamSynchronize(c->stream));
+    return KC_OK;
+}
+
+int kc_time(const kc_ctx *c, double *t, int64_t *steps)
+{
+    if (!c)
+        return KC_EINVAL;
+    if (t)
+        *t = (double)c->steps * c->dt;
+    if (steps)
+        *steps = c->steps;
+    return KC_OK;
+}
+
+int kc_set_tuning(kc_ctx *c, int32_t tsteps, int32_t rows, int32_t prefetch)
+{
+    if (!c)
+        return KC_EINVAL;
+    c->err.clear();
+    if (tsteps < 0 || tsteps > 8 || rows < 0 || (prefetch != 0 && prefetch != 2 && prefetch != 4))
+        return fail(c, KC_EINVAL, "bad tuning (%d, %d, %d)", tsteps, rows, prefetch);
+    if (tsteps)
+        c->tune.tsteps = kc::stream_depth_at_most(tsteps);
+    if (rows)
+        c->tune.rows = rows;
+    if (prefetch)
+        c->tune.prefetch = prefetch;
+    return KC_OK;
+}
+
+int kc_get_tuning(const kc_ctx *c, int32_t *tsteps, int32_t *rows, int32_t *prefetch)
+{
+    if (!c)
+        return KC_EINVAL;
+    if (tsteps)
+        *tsteps = c->tune.tsteps;
+    if (rows)
+        *rows = c->tune.rows;
+    if (prefetch)
+        *prefetch = c->tune.prefetch;
+    return KC_OK;
+}
+
+int kc_set_reference_kernel(kc_ctx *c, int32_t on)
+{
+    if (!c)
+        return KC_EINVAL;
+    c->ref = on != 0;
+    return KC_OK;
+}
+
+} // extern "C"

@@ -1,0 +1,122 @@
+// kc_device.h -- per-cell arithmetic of the explicit step, shared by every
+// kernel of the library so that all launch shapes produce identical bits.
+//
+// Discrete operator (finite volumes of width h, forward Euler; Sec. 2.4
+// eqs. eqnadim / eqbadim with no-flux faces, eq. bconds):
+//
+//   G(P,Q)  = inflow into P across the face shared with Q, times h^2:
+//             gb = (Dh_P + Dh_Q)(b_Q - b_P) - X_up (n_Q - n_P)
+//             gn = n_Q - n_P
+//     Dh    = sigma n b / 2            (half the Kawasaki diffusivity, eq. CoefCrsDif)
+//     X     = chi sigma n b^2 chihat(n) (chemotactic coefficient, eq. chemflux
+//                                        normalised as in eq. eqbadim)
+//     X_up  = X_P if n_Q > n_P else X_Q (donor cell of the chemotactic flux)
+//   F(P)    = (G(P,E) - G(W,P)) + (G(P,N) - G(S,P))   (E/W along x, N = row+1)
+//   b'      = b + lam F_b + dt theta kappa n b
+//   n'      = n + lam D_n F_n - dt kappa n b          (lam = dt / h^2)
+//
+// A boundary face contributes exactly zero.  The library is compiled without
+// FMA contraction; the FMAs below are explicit, so every kernel that calls
+// these functions on the same inputs produces the same bits.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace kc {
+
+// Constants of one run, in the field precision R.
+template <typename R> struct Coef {
+    R lam;   // dt / h^2
+    R lamDn; // dt D_n / h^2
+    R gro;   // dt theta kappa
+    R upt;   // dt kappa
+    R chi2;  // 2 chi   (X = chi2 * Dh * b * chihat)
+};
+
+template <typename R> __device__ __forceinline__ R rcp(R x);
+// v_rcp_f32: 1 ulp reciprocal; (1+n)^2 >= 1 so no denormal or overflow case.
+template <> __device__ __forceinline__ float rcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+// correctly rounded double division
+template <> __device__ __forceinline__ double rcp<double>(double x) { return 1.0 / x; }
+
+__device__ __forceinline__ float fmaR(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmaR(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// Per-cell coefficients from (sigma/2, n, b).
+template <typename R, int LAW>
+__device__ __forceinline__ void coef(R sh, R n, R b, R chi2, R &Dh, R &X)
+{
+    Dh = (sh * n) * b;
+    const R xb = (chi2 * Dh) * b;
+    if (LAW == 0) {
+        const R t = R(1) + n;
+        X = xb * rcp<R>(t * t);
+    } else {
+        X = xb;
+    }
+}
+
+// Face inflow G(P,Q); `valid` false for a boundary face (zero flux).
+template <typename R>
+__device__ __forceinline__ void face(R bP, R nP, R DP, R XP, R bQ, R nQ, R DQ, R XQ, bool valid,
+                                     R &gb, R &gn)
+{
+    const R dn = nQ - nP;
+    const R db = bQ - bP;
+    const R xu = (nQ > nP) ? XP : XQ;
+    const R g = fmaR(-xu, dn, (DP + DQ) * db);
+    gb = valid ? g : R(0);
+    gn = valid ? dn : R(0);
+}
+
+// Net inflow from the four face values, in one fixed order.
+template <typename R>
+__device__ __forceinline__ R net(R ge, R gw, R gnorth, R gsouth)
+{
+    return (ge - gw) + (gnorth - gsouth);
+}
+
+// Forward-Euler update of one cell.
+template <typename R>
+__device__ __forceinline__ void update(R b, R n, R Fb, R Fn, const Coef<R> &c, R &bo, R &no)
+{
+    const R nb = n * b;
+    bo = fmaR(c.gro, nb, fmaR(c.lam, Fb, b));
+    no = fmaR(-c.upt, nb, fmaR(c.lamDn, Fn, n));
+}
+
+// ---------------------------------------------------------------------------
+// Cross-lane moves inside a 64-lane wavefront (DPP wave shifts, GFX9 family).
+//   from_next(v): lane i receives lane i+1's v (lane 63 receives 0)
+//   from_prev(v): lane i receives lane i-1's v (lane 0 receives 0)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int dpp_next_i(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xF, 0xF, false); }
+__device__ __forceinline__ int dpp_prev_i(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xF, 0xF, false); }
+
+__device__ __forceinline__ float from_next(float v) { return __int_as_float(dpp_next_i(__float_as_int(v))); }
+__device__ __forceinline__ float from_prev(float v) { return __int_as_float(dpp_prev_i(__float_as_int(v))); }
+__device__ __forceinline__ double from_next(double v)
+{
+    const int64_t u = __double_as_longlong(v);
+    const int lo = dpp_next_i((int)(uint32_t)u), hi = dpp_next_i((int)(u >> 32));
+    return __longlong_as_double((int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
+}
+__device__ __forceinline__ double from_prev(double v)
+{
+    const int64_t u = __double_as_longlong(v);
+    const int lo = dpp_prev_i((int)(uint32_t)u), hi = dpp_prev_i((int)(u >> 32));
+    return __longlong_as_double((int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
+}
+
+// Workgroup index remapped so that each of the 8 XCDs (which receive
+// workgroups round-robin) owns one contiguous range of logical tiles and its
+// L2 sees the halo rows that neighbouring tiles share.
+__device__ __forceinline__ int xcd_block(int nblocks_padded)
+{
+    const int per = nblocks_padded >> 3;
+    const int b = blockIdx.x;
+    return (b & 7) * per + (b >> 3);
+}
+
+} // namespace kc

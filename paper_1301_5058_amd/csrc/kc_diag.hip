@@ -1,0 +1,169 @@
+// kc_diag.hip -- reductions over one field level, accumulated in double.
+//
+// diag_partial: block k reduces rows k, k + G, k + 2G, ...: sum b, sum n and
+//   the largest squared distance from (cx, cy) of a cell with b >= b_thr
+//   (-1 when none).  Wavefront butterfly (xor shuffles) then a fixed LDS tree,
+//   so the result is the same bits on every run for a given grid.
+// diag_final:   one block folds the partials in a fixed order and writes
+//   {t, h^2 sum b, h^2 sum n, h sqrt(max d^2)}.
+// check_partial: input validation of dense device arrays: per block, the
+//   count of NaN / Inf / negative entries and the max of sigma n b.
+#include "kc_internal.h"
+
+namespace kc {
+
+static constexpr int kDiagBlocks = 1024;
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1)
+        v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ double wave_max(double v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1)
+        v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// Reduce three per-thread values over a 256-thread block; thread 0 gets them.
+__device__ __forceinline__ void block_reduce3(double &s0, double &s1, double &m2)
+{
+    __shared__ double sh[3][4];
+    s0 = wave_sum(s0);
+    s1 = wave_sum(s1);
+    m2 = wave_max(m2);
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    if (l == 0) {
+        sh[0][w] = s0;
+        sh[1][w] = s1;
+        sh[2][w] = m2;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        s0 = (sh[0][0] + sh[0][1]) + (sh[0][2] + sh[0][3]);
+        s1 = (sh[1][0] + sh[1][1]) + (sh[1][2] + sh[1][3]);
+        m2 = fmax(fmax(sh[2][0], sh[2][1]), fmax(sh[2][2], sh[2][3]));
+    }
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void diag_partial(const R *b, const R *n, int nx, int ny,
+                                                     int pitch, double b_thr, double cx, double cy,
+                                                     double *parts)
+{
+    double sb = 0.0, sn = 0.0, m2 = -1.0;
+    for (int y = blockIdx.x; y < ny; y += gridDim.x) {
+        const R *rb = b + (size_t)y * pitch;
+        const R *rn = n + (size_t)y * pitch;
+        const double dy = (double)y - cy;
+        for (int x = threadIdx.x; x < nx; x += 256) {
+            const double bv = (double)rb[x];
+            sb += bv;
+            sn += (double)rn[x];
+            if (bv >= b_thr) {
+                const double dx = (double)x - cx;
+                m2 = fmax(m2, dx * dx + dy * dy);
+            }
+        }
+    }
+    block_reduce3(sb, sn, m2);
+    if (threadIdx.x == 0) {
+        parts[3 * blockIdx.x + 0] = sb;
+        parts[3 * blockIdx.x + 1] = sn;
+        parts[3 * blockIdx.x + 2] = m2;
+    }
+}
+
+__global__ __launch_bounds__(256) void diag_final(const double *parts, int nparts, double h,
+                                                   double t, double *out4)
+{
+    double sb = 0.0, sn = 0.0, m2 = -1.0;
+    for (int i = threadIdx.x; i < nparts; i += 256) {
+        sb += parts[3 * i + 0];
+        sn += parts[3 * i + 1];
+        m2 = fmax(m2, parts[3 * i + 2]);
+    }
+    block_reduce3(sb, sn, m2);
+    if (threadIdx.x == 0) {
+        out4[0] = t;
+        out4[1] = h * h * sb;
+        out4[2] = h * h * sn;
+        out4[3] = m2 < 0.0 ? 0.0 : h * sqrt(m2);
+    }
+}
+
+int diag_parts(int ny) { return ny < kDiagBlocks ? ny : kDiagBlocks; }
+
+template <typename R>
+hipError_t launch_diag(const R *b, const R *n, int nx, int ny, int pitch, double h, double t,
+                       double b_thr, double cx, double cy, double *parts, double *out4,
+                       hipStream_t s)
+{
+    const int np = diag_parts(ny);
+    hipLaunchKernelGGL((diag_partial<R>), dim3(np), dim3(256), 0, s, b, n, nx, ny, pitch, b_thr, cx,
+                       cy, parts);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(diag_final, dim3(1), dim3(256), 0, s, parts, np, h, t, out4);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Input validation
+// ---------------------------------------------------------------------------
+static constexpr int kCheckBlocks = 1024;
+
+template <typename R>
+__global__ __launch_bounds__(256) void check_partial(const R *b, const R *n, const R *sg,
+                                                      size_t cells, double *parts)
+{
+    double nbad = 0.0, mx = 0.0, unused = 0.0;
+    const size_t stride = (size_t)gridDim.x * 256;
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < cells; i += stride) {
+        const R bv = b[i], nv = n[i], sv = sg[i];
+        const bool ok = (bv >= R(0)) && (nv >= R(0)) && (sv >= R(0)) && __builtin_isfinite(bv) &&
+                        __builtin_isfinite(nv) && __builtin_isfinite(sv);
+        if (!ok)
+            nbad += 1.0;
+        else
+            mx = fmax(mx, (double)sv * (double)nv * (double)bv);
+    }
+    block_reduce3(nbad, unused, mx);
+    if (threadIdx.x == 0) {
+        parts[2 * blockIdx.x + 0] = nbad;
+        parts[2 * blockIdx.x + 1] = mx;
+    }
+}
+
+int check_parts(size_t cells)
+{
+    const size_t nb = (cells + 255) / 256;
+    return nb < (size_t)kCheckBlocks ? (int)(nb ? nb : 1) : kCheckBlocks;
+}
+
+template <typename R>
+hipError_t launch_check(const R *b, const R *n, const R *sg, size_t cells, double *parts,
+                        hipStream_t s)
+{
+    hipLaunchKernelGGL((check_partial<R>), dim3(check_parts(cells)), dim3(256), 0, s, b, n, sg,
+                       cells, parts);
+    return hipGetLastError();
+}
+
+template hipError_t launch_diag<float>(const float *, const float *, int, int, int, double, double,
+                                       double, double, double, double *, double *, hipStream_t);
+template hipError_t launch_diag<double>(const double *, const double *, int, int, int, double,
+                                        double, double, double, double, double *, double *,
+                                        hipStream_t);
+template hipError_t launch_check<float>(const float *, const float *, const float *, size_t,
+                                        double *, hipStream_t);
+template hipError_t launch_check<double>(const double *, const double *, const double *, size_t,
+                                         double *, hipStream_t);
+
+} // namespace kc

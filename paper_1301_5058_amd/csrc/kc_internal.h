@@ -1,0 +1,62 @@
+// kc_internal.h -- launch interface between the C ABI (kc_api.hip) and the
+// kernels (kc_step.hip, kc_diag.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "kc_device.h"
+
+namespace kc {
+
+// Padded device layout of one field: row y starts at y * pitch elements;
+// pitch is nx rounded up to a multiple of 64 elements, padding kept at 0.
+inline int pitch_for(int nx) { return (nx + 63) / 64 * 64; }
+
+template <typename R> struct Fields {
+    const R *b_in, *n_in, *sg; // current level and agar field sigma
+    R *b_out, *n_out;          // next level
+    int nx, ny, pitch;
+};
+
+struct Tuning {
+    int tsteps;   // steps fused in one launch
+    int rows;     // output rows per wavefront strip
+    int prefetch; // rows loaded ahead (2 or 4)
+};
+
+// Largest fused depth with a compiled kernel that is <= t.
+int stream_depth_at_most(int t);
+
+// Launch geometry of the fused kernel (for the planner and the autotuner).
+struct StreamGeom {
+    int nsx, nsy, nstrips, nblocks_padded, out_cols;
+};
+StreamGeom stream_geom(int precision, int tsteps, int nx, int ny, int rows);
+
+// One launch advancing `tsteps` steps with the fused kernel.
+template <typename R>
+hipError_t launch_stream(const Fields<R> &f, const Coef<R> &c, int chi_law, const Tuning &t,
+                         hipStream_t s);
+// One launch advancing one step with the global-memory reference kernel.
+template <typename R>
+hipError_t launch_ref(const Fields<R> &f, const Coef<R> &c, int chi_law, hipStream_t s);
+
+// Diagnostics: partial sums over row blocks, then one fixed-order final pass
+// writing {t, mass, nutrient, radius} to out4 (device doubles).
+int diag_parts(int ny);
+template <typename R>
+hipError_t launch_diag(const R *b, const R *n, int nx, int ny, int pitch, double h, double t,
+                       double b_thr, double cx, double cy, double *parts, double *out4,
+                       hipStream_t s);
+
+// Input check of dense device arrays: block k writes parts[2k] = number of
+// NaN / Inf / negative entries it saw and parts[2k+1] = its max of sigma n b,
+// for k < check_parts(cells).
+int check_parts(size_t cells);
+template <typename R>
+hipError_t launch_check(const R *b, const R *n, const R *sg, size_t cells, double *parts,
+                        hipStream_t s);
+
+} // namespace kc

@@ -1,0 +1,131 @@
+"""Python face of the single-instance solver (kc_* calls of include/kc.h).
+
+Solver wraps one kc_ctx.  Fields go in and out as numpy arrays (host memory)
+or torch tensors on the GPU (device memory); the context's stream is torch's
+current stream unless one is given.  Every computation happens in libkc.so.
+"""
+import ctypes
+import math
+
+import numpy as np
+import torch
+
+from . import native as N
+
+
+def _np_dtype(precision):
+    return np.float32 if precision == N.KC_FP32 else np.float64
+
+
+def _torch_dtype(precision):
+    return torch.float32 if precision == N.KC_FP32 else torch.float64
+
+
+class Solver:
+    def __init__(self, nx, ny, h=1.0, dt=0.2, chi=0.0, chi_law="receptor", precision="fp32",
+                 D_n=1.0, theta=1.0, kappa=1.0, b_thr=0.5, cx=None, cy=None, step0=0,
+                 stream=None):
+        self.nx, self.ny, self.h, self.dt = int(nx), int(ny), float(h), float(dt)
+        p = N.default_params()
+        p.D_n, p.theta, p.kappa, p.chi = float(D_n), float(theta), float(kappa), float(chi)
+        p.chi_law = N.KC_CHI_RECEPTOR if chi_law == "receptor" else N.KC_CHI_CONSTANT
+        p.precision = N.KC_FP32 if precision == "fp32" else N.KC_FP64
+        p.b_thr = float(b_thr)
+        p.cx = math.nan if cx is None else float(cx)
+        p.cy = math.nan if cy is None else float(cy)
+        p.step0 = int(step0)
+        self.precision = p.precision
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        g = N.KcGrid(self.nx, self.ny)
+        ctx = ctypes.c_void_p()
+        N.check(N.lib().kc_create(ctypes.byref(g), self.h, self.dt, ctypes.byref(p),
+                                  ctypes.c_void_p(stream.cuda_stream), ctypes.byref(ctx)))
+        self.ctx = ctx
+
+    # -- fields ---------------------------------------------------------------
+    def _arg(self, a):
+        """(pointer, mem kind, keep-alive) for a numpy array or torch tensor."""
+        if isinstance(a, torch.Tensor):
+            if a.dtype != _torch_dtype(self.precision) or tuple(a.shape) != (self.ny, self.nx):
+                raise ValueError("field must be %s of shape (%d, %d)"
+                                 % (_torch_dtype(self.precision), self.ny, self.nx))
+            a = a.contiguous()
+            if a.is_cuda:
+                return ctypes.c_void_p(a.data_ptr()), N.KC_MEM_DEVICE, a
+            a = a.numpy()
+        a = np.ascontiguousarray(a, dtype=_np_dtype(self.precision))
+        if a.shape != (self.ny, self.nx):
+            raise ValueError("field must have shape (%d, %d)" % (self.ny, self.nx))
+        return ctypes.c_void_p(a.ctypes.data), N.KC_MEM_HOST, a
+
+    def set_fields(self, b, n, sigma):
+        (pb, mb, kb), (pn, mn, kn), (ps, ms, ks) = self._arg(b), self._arg(n), self._arg(sigma)
+        if not (mb == mn == ms):
+            raise ValueError("b, n and sigma must all be host arrays or all device tensors")
+        N.check(N.lib().kc_set_fields(self.ctx, pb, pn, ps, mb), self.ctx)
+
+    def get_fields(self, device=False):
+        if device:
+            b = torch.empty((self.ny, self.nx), dtype=_torch_dtype(self.precision), device="cuda")
+            n = torch.empty_like(b)
+            N.check(N.lib().kc_get_fields(self.ctx, ctypes.c_void_p(b.data_ptr()),
+                                          ctypes.c_void_p(n.data_ptr()), N.KC_MEM_DEVICE), self.ctx)
+            return b, n
+        b = np.empty((self.ny, self.nx), dtype=_np_dtype(self.precision))
+        n = np.empty_like(b)
+        N.check(N.lib().kc_get_fields(self.ctx, ctypes.c_void_p(b.ctypes.data),
+                                      ctypes.c_void_p(n.ctypes.data), N.KC_MEM_HOST), self.ctx)
+        return b, n
+
+    # -- time stepping ----------------------------------------------------------
+    def step(self, nsteps):
+        N.check(N.lib().kc_step(self.ctx, int(nsteps)), self.ctx)
+
+    def diagnostics(self):
+        m, nu, r = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        N.check(N.lib().kc_diagnostics(self.ctx, ctypes.byref(m), ctypes.byref(nu),
+                                       ctypes.byref(r)), self.ctx)
+        return m.value, nu.value, r.value
+
+    def diagnostics_device(self, out4):
+        """Enqueue {t, mass, nutrient, radius} into a float64 CUDA tensor view of 4 elements."""
+        if out4.dtype != torch.float64 or not out4.is_cuda or out4.numel() < 4 or \
+                not out4.is_contiguous():
+            raise ValueError("out4 must be a contiguous float64 CUDA tensor with >= 4 elements")
+        N.check(N.lib().kc_diagnostics_device(self.ctx, ctypes.c_void_p(out4.data_ptr())), self.ctx)
+
+    def time(self):
+        t, s = ctypes.c_double(), ctypes.c_int64()
+        N.check(N.lib().kc_time(self.ctx, ctypes.byref(t), ctypes.byref(s)))
+        return t.value, s.value
+
+    # -- kernel configuration ---------------------------------------------------
+    def set_tuning(self, tsteps=0, rows=0, prefetch=0):
+        N.check(N.lib().kc_set_tuning(self.ctx, int(tsteps), int(rows), int(prefetch)), self.ctx)
+
+    def tuning(self):
+        t, r, p = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        N.check(N.lib().kc_get_tuning(self.ctx, ctypes.byref(t), ctypes.byref(r), ctypes.byref(p)))
+        return t.value, r.value, p.value
+
+    def use_reference_kernel(self, on=True):
+        N.check(N.lib().kc_set_reference_kernel(self.ctx, 1 if on else 0), self.ctx)
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            N.lib().kc_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

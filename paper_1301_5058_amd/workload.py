@@ -22,23 +22,43 @@ values.
 import numpy as np
 
 
-def fields(nx, ny, n0, a, seed, b_max=0.7, r0=6.0, cut=3.0, sigma0=1.0):
-    """Return (b0, n0_field, sigma) as float32 arrays of shape [ny, nx]."""
-    j, i = np.meshgrid(np.arange(ny, dtype=np.float64), np.arange(nx, dtype=np.float64),
-                       indexing="ij")
-    d2 = (i - (nx - 1) / 2.0) ** 2 + (j - (ny - 1) / 2.0) ** 2
-    b = b_max * np.exp(-d2 / (r0 * r0))
-    b[d2 > (cut * r0) ** 2] = 0.0
-    n = np.full((ny, nx), float(n0))
-    u = np.random.default_rng(seed).uniform(-1.0, 1.0, (ny, nx))
-    s = sigma0 * (1.0 + a * u)
-    return b.astype(np.float32), n.astype(np.float32), s.astype(np.float32)
+def fields(nx, ny, n0, a, seed, b_max=0.7, r0=6.0, cut=3.0, sigma0=1.0, chunk_rows=1024):
+    """Return (b0, n0_field, sigma) as float32 arrays of shape [ny, nx].
+
+    The inoculum is evaluated only on the square patch that holds its support,
+    and sigma is drawn in row chunks (the same stream of doubles as one draw of
+    shape [ny, nx]), so that grids of 16384^2 cells stay cheap in host memory.
+    """
+    cx, cy = (nx - 1) / 2.0, (ny - 1) / 2.0
+    rc = cut * r0
+    i0, i1 = max(0, int(np.floor(cx - rc))), min(nx, int(np.ceil(cx + rc)) + 1)
+    j0, j1 = max(0, int(np.floor(cy - rc))), min(ny, int(np.ceil(cy + rc)) + 1)
+    b = np.zeros((ny, nx), dtype=np.float32)
+    if i1 > i0 and j1 > j0:
+        j, i = np.meshgrid(np.arange(j0, j1, dtype=np.float64), np.arange(i0, i1, dtype=np.float64),
+                           indexing="ij")
+        d2 = (i - cx) ** 2 + (j - cy) ** 2
+        patch = b_max * np.exp(-d2 / (r0 * r0))
+        patch[d2 > rc * rc] = 0.0
+        b[j0:j1, i0:i1] = patch.astype(np.float32)
+    n = np.full((ny, nx), np.float32(n0), dtype=np.float32)
+    s = np.empty((ny, nx), dtype=np.float32)
+    rng = np.random.default_rng(seed)
+    for r in range(0, ny, chunk_rows):
+        rows = min(chunk_rows, ny - r)
+        u = rng.uniform(-1.0, 1.0, (rows, nx))
+        s[r:r + rows] = (sigma0 * (1.0 + a * u)).astype(np.float32)
+    return b, n, s
 
 
 def config_dt(b, n, sigma, h=1.0, D_n=1.0, factor=0.2):
     """dt = factor h^2 / max(D_n, max sigma n b) on the given fields, FP32-rounded."""
-    m = float(np.max(np.asarray(sigma, np.float64) * np.asarray(n, np.float64)
-                     * np.asarray(b, np.float64)))
+    b = np.asarray(b)
+    nz = b > 0
+    m = 0.0
+    if nz.any():
+        m = float(np.max(np.asarray(sigma)[nz].astype(np.float64) * np.asarray(n)[nz].astype(np.float64)
+                         * b[nz].astype(np.float64)))
     return float(np.float32(factor * h * h / max(D_n, m)))
 
 

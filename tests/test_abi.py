@@ -1,0 +1,133 @@
+"""C ABI checks that need no GPU: the library loads, exports every symbol its
+headers declare, and rejects bad arguments before any device work."""
+import ctypes
+import glob
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1301_5058_amd import native as N
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = set()
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        src = open(h).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        for m in re.finditer(r"^[A-Za-z_][\w \*]*?\b(k[a-z]_\w+)\s*\(", src, flags=re.M):
+            names.add(m.group(1))
+    return sorted(names)
+
+
+def test_headers_declare_the_entry_points():
+    names = _declared()
+    for must in ("kc_create", "kc_set_fields", "kc_step", "kc_diagnostics", "kc_destroy"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    L = N.lib()
+    missing = [n for n in _declared() if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_strerror_and_null_context():
+    L = N.lib()
+    for code in (0, -1, -2, -3, -4, -5, -6):
+        assert L.kc_strerror(code)
+    assert L.kc_strerror(-99) == b"unknown status"
+    L.kc_destroy(None)
+    assert L.kc_step(None, 1) == N.KC_EINVAL
+    assert L.kc_set_fields(None, None, None, None, 0) == N.KC_EINVAL
+    assert L.kc_diagnostics(None, None, None, None) == N.KC_EINVAL
+    assert L.kc_get_fields(None, None, None, 0) == N.KC_EINVAL
+    assert L.kc_set_tuning(None, 1, 1, 2) == N.KC_EINVAL
+    assert L.kc_time(None, None, None) == N.KC_EINVAL
+    assert L.kc_last_error(None) == b"null context"
+
+
+def _create(nx=16, ny=16, h=1.0, dt=0.1, **kw):
+    L = N.lib()
+    p = N.default_params()
+    for k, v in kw.items():
+        setattr(p, k, v)
+    g = N.KcGrid(nx, ny)
+    ctx = ctypes.c_void_p()
+    rc = L.kc_create(ctypes.byref(g), h, dt, ctypes.byref(p), None, ctypes.byref(ctx))
+    if rc == N.KC_OK:
+        L.kc_destroy(ctx)
+    return rc, ctx
+
+
+@pytest.mark.parametrize("kw", [dict(nx=0), dict(ny=-3), dict(h=0.0), dict(h=math.nan),
+                                dict(dt=0.0), dict(dt=-1.0), dict(dt=math.inf),
+                                dict(D_n=-1.0), dict(theta=-0.1), dict(kappa=math.nan),
+                                dict(chi=-2.0), dict(chi_law=7), dict(precision=3),
+                                dict(nx=1 << 21), dict(step0=-1), dict(b_thr=math.nan)])
+def test_create_rejects_bad_arguments(kw):
+    rc, ctx = _create(**kw)
+    assert rc == N.KC_EINVAL
+    assert not ctx.value
+
+
+def test_create_rejects_null_outputs():
+    L = N.lib()
+    p = N.default_params()
+    g = N.KcGrid(8, 8)
+    assert L.kc_create(ctypes.byref(g), 1.0, 0.1, ctypes.byref(p), None, None) == N.KC_EINVAL
+    ctx = ctypes.c_void_p()
+    assert L.kc_create(None, 1.0, 0.1, ctypes.byref(p), None, ctypes.byref(ctx)) == N.KC_EINVAL
+    assert L.kc_create(ctypes.byref(g), 1.0, 0.1, None, None, ctypes.byref(ctx)) == N.KC_EINVAL
+
+
+def test_create_without_device_reports_hip_error():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    rc, ctx = _create()
+    assert rc == N.KC_EHIP and not ctx.value
+
+
+def _check(b, n, s, precision=N.KC_FP32, nx=None, ny=None):
+    L = N.lib()
+    dt = np.float32 if precision == N.KC_FP32 else np.float64
+    b, n, s = (np.ascontiguousarray(a, dtype=dt) for a in (b, n, s))
+    ny_, nx_ = b.shape
+    mx = ctypes.c_double(-1)
+    rc = L.kc_check_fields(nx_ if nx is None else nx, ny_ if ny is None else ny, precision,
+                           b.ctypes.data, n.ctypes.data, s.ctypes.data, ctypes.byref(mx))
+    return rc, mx.value
+
+
+@pytest.mark.parametrize("precision", [N.KC_FP32, N.KC_FP64])
+def test_check_fields(precision):
+    rng = np.random.default_rng(0)
+    b = rng.uniform(0, 0.7, (5, 6))
+    n = rng.uniform(0, 1, (5, 6))
+    s = rng.uniform(0.5, 1.5, (5, 6))
+    rc, mx = _check(b, n, s, precision)
+    assert rc == N.KC_OK
+    dt = np.float32 if precision == N.KC_FP32 else np.float64
+    ref = np.max(b.astype(dt).astype(np.float64) * n.astype(dt) * s.astype(dt))
+    assert mx == pytest.approx(ref, rel=1e-15)
+    for bad in (math.nan, math.inf, -1e-30):
+        for which in range(3):
+            arrs = [b.copy(), n.copy(), s.copy()]
+            arrs[which][2, 3] = bad
+            assert _check(*arrs, precision)[0] == N.KC_ENONFINITE
+    assert _check(b, n, s, precision, nx=0)[0] == N.KC_EINVAL
+    assert _check(b, n, s, 9)[0] == N.KC_EINVAL
+    L = N.lib()
+    assert L.kc_check_fields(6, 5, precision, None, None, None, None) == N.KC_EINVAL
+
+
+def test_suggest_dt():
+    L = N.lib()
+    assert L.kc_suggest_dt(1.0, 1.0, 0.3) == pytest.approx(0.2)
+    assert L.kc_suggest_dt(0.5, 1.0, 2.0) == pytest.approx(0.2 * 0.25 / 2.0)
+    assert L.kc_suggest_dt(0.0, 1.0, 1.0) == 0.0
