@@ -65,7 +65,7 @@ def cpu_baseline(b, n, s, dt, chi, budget_s=15.0):
     t0 = time.perf_counter()
     oracle.run(b64, n64, s64, 1.0, dt, 2, chi=chi)
     per = (time.perf_counter() - t0) / 2
-    steps = int(max(4, min(400, budget_s / max(per, 1e-9))))
+    steps = int(max(4, min(20000, budget_s / max(per, 1e-9))))
     t0 = time.perf_counter()
     oracle.run(b64, n64, s64, 1.0, dt, steps, chi=chi)
     el = time.perf_counter() - t0
