@@ -27,7 +27,8 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, 8 TB/s
 BYTES_PER_CELL_LAUNCH = {"fp32": 20, "fp64": 40}  # read b, n, sigma; write b', n'
 SAMPLE_EVERY = 100
 METRIC = "GCell-updates/s & % HBM peak (4096^2 FP32); velocity-map pts/s at <=2% err"
-STEP_SOURCES = ("paper_1301_5058_amd/csrc/kc_step.hip", "paper_1301_5058_amd/csrc/kc_device.h")
+STEP_SOURCES = ("paper_1301_5058_amd/csrc/kc_step.hip", "paper_1301_5058_amd/csrc/kc_stream.h",
+                "paper_1301_5058_amd/csrc/kc_device.h")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_stream_4096_fp32_traffic.txt")
 
 

@@ -1,0 +1,108 @@
+/*
+ * kb.h -- batched parameter sweeps of the chemotaxis system (see kc.h for the
+ * equations and the discretisation): many independent instances, each with
+ * its own grid, time step, rates, chemotactic strength and agar field, advanced
+ * together by one persistent kernel launch per kb_run call.
+ *
+ * The paper varies the initial nutrient n0, the chemotactic strength chi0 and
+ * the agar field (Sec. 3, table tabresparam) and compares the growth velocity
+ * of the colony envelope with its asymptotic bound (Sec. 4.1-4.2).  A batch
+ * runs such a sweep: every instance is a kc-style grid in FP32 whose
+ * envelope radius R(t), mass and nutrient are sampled on the device at a fixed
+ * step interval, and whose velocity is the least-squares slope of R(t) over a
+ * radius window.
+ *
+ * Memory and streams follow kc.h: fields passed in or out are dense row-major
+ * [ny][nx] float arrays in host or device memory (KC_MEM_HOST /
+ * KC_MEM_DEVICE), the batch keeps padded copies in one device arena, and all
+ * work is enqueued on the stream given at creation.  Status codes are kc.h's.
+ *
+ * Persistent launch.  kb_run issues one kernel whose workgroups pull work
+ * items (time block, instance, strip) from a global counter in time-block
+ * order; an item of block tau waits until every strip of block tau-1 of the
+ * same instance has been stored (per-instance completion counters with
+ * device-scope release / acquire).  Every item waited on was handed out
+ * earlier, to a running workgroup, so the launch always drains.  Each wait is
+ * also bounded (kb_set_spin_limit): a wait that exceeds the bound stops the
+ * launch and kb_run reports KC_EHIP.
+ */
+#ifndef KB_H
+#define KB_H
+
+#include <stdint.h>
+
+#include "kc.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct kb_batch kb_batch;
+
+typedef struct {
+    int32_t nx, ny;   /* grid cells, >= 1 each                                      */
+    double h, dt;     /* cell width, time step (> 0)                                */
+    double D_n, theta, kappa, chi; /* rates and chemotactic strength, >= 0 (kc_params) */
+    double b_thr;     /* envelope threshold                                         */
+    double cx, cy;    /* envelope centre in cell units; NaN = grid centre           */
+} kb_instance;
+
+/* Create a batch of count >= 1 instances sharing chi_law (KC_CHI_*), able to
+ * hold max_samples >= 1 diagnostic samples per instance.  Allocates one
+ * device arena for all fields.  *out is NULL on failure. */
+int kb_create(int32_t count, const kb_instance *inst, int32_t chi_law, int32_t max_samples,
+              void *hip_stream, kb_batch **out);
+
+/* Set the initial fields of instance k (0 <= k < count); checks and
+ * stability bound as kc_set_fields.  Clears the recorded samples of the whole
+ * batch and its step count. */
+int kb_set_fields(kb_batch *bt, int32_t k, const float *b0, const float *n0, const float *sigma,
+                  int mem);
+
+/* Advance every instance by nsteps (a multiple of sample_every >= 1) and
+ * record {t, mass, nutrient, envelope_radius} of every instance after each
+ * sample_every steps.  One persistent launch (or, with persistent = 0 in
+ * kb_set_tuning, one launch per time block).  Enqueued; fails with
+ * KC_EINVAL when the samples would exceed max_samples. */
+int kb_run(kb_batch *bt, int64_t nsteps, int32_t sample_every);
+
+/* Copy the samples out: out is [count][max_samples][4] doubles (unused
+ * entries are zero); *nsamples (may be NULL) receives the number recorded.
+ * Synchronous. */
+int kb_series(kb_batch *bt, double *out, int32_t *nsamples, int mem);
+
+/* Current fields of instance k (synchronous). */
+int kb_get_fields(kb_batch *bt, int32_t k, float *b, float *n, int mem);
+
+/* Least-squares slope dR/dt of each instance's recorded envelope radius over
+ * the samples with r_lo[k] <= R <= r_hi[k] (host arrays of count doubles).
+ * v[k] is NaN when fewer than 3 samples qualify; npoints (may be NULL)
+ * receives the sample counts.  Computed on the device; synchronous. */
+int kb_fit_velocity(kb_batch *bt, const double *r_lo, const double *r_hi, double *v,
+                    int32_t *npoints);
+
+/* Kernel configuration.  tsteps: steps per time block (a compiled depth that
+ * divides sample_every is used); rows: output rows per strip for each
+ * instance (count entries, or NULL to keep); prefetch 2 or 4 (0 keeps);
+ * persistent: 1 = one launch per kb_run, 0 = one launch per time block,
+ * -1 keeps.  Results are bitwise independent of all of these. */
+int kb_set_tuning(kb_batch *bt, int32_t tsteps, const int32_t *rows, int32_t prefetch,
+                  int32_t persistent);
+int kb_get_tuning(const kb_batch *bt, int32_t *tsteps, int32_t *rows, int32_t *prefetch,
+                  int32_t *persistent);
+
+/* Bound of each wait of the persistent kernel, in polls (default 2^23, a few
+ * seconds).  A tiny bound makes a run stop early with KC_EHIP. */
+int kb_set_spin_limit(kb_batch *bt, int64_t polls);
+
+/* Steps done since kb_set_fields. */
+int kb_steps(const kb_batch *bt, int64_t *steps);
+
+void kb_destroy(kb_batch *bt);
+const char *kb_last_error(const kb_batch *bt);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KB_H */

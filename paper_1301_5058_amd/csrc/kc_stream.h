@@ -1,0 +1,217 @@
+// kc_stream.h -- one wavefront advancing one strip of the grid by T steps.
+//
+// A 64-lane wavefront owns a strip of 64*VEC columns (VEC adjacent cells per
+// lane, loaded as one 16-byte vector) and walks it downwards row by row.
+// Level s (1..T) of the time block trails level s-1 by one row, so the three
+// rows a level needs are held in registers; the horizontal neighbour across a
+// lane boundary comes from the adjacent lane through a DPP wave shift.  Each
+// level loses one valid column at either strip edge, so strips overlap by
+// HX >= T columns (a multiple of VEC) and by T rows above and below.  Input
+// rows are prefetched PF rows ahead into a register ring.  HBM traffic per
+// launch: read b, n, sigma once, write b', n' once, plus halo re-reads that
+// mostly hit L2.
+//
+// With DIAG set, the cells a strip stores are also folded into a per-lane
+// accumulator (sum b, sum n in double, largest squared distance from the
+// envelope centre of a cell with b >= b_thr), in a fixed order.
+#pragma once
+
+#include "kc_device.h"
+
+namespace kc {
+
+template <typename R, int VEC> struct VecT;
+template <> struct VecT<float, 4> { typedef float type __attribute__((ext_vector_type(4))); };
+template <> struct VecT<double, 2> { typedef double type __attribute__((ext_vector_type(2))); };
+
+template <typename R> struct StreamShape;
+template <> struct StreamShape<float> { static constexpr int VEC = 4; };
+template <> struct StreamShape<double> { static constexpr int VEC = 2; };
+
+template <int T, int VEC> struct Halo {
+    static constexpr int HX = (T + VEC - 1) / VEC * VEC; // halo columns per side
+    static constexpr int WC = 64 * VEC;                  // columns per wavefront
+    static constexpr int OW = WC - 2 * HX;               // output columns per strip
+};
+
+template <typename R> struct StripArgs {
+    const R *b_in, *n_in, *sg;
+    R *b_out, *n_out;
+    int nx, ny, pitch;
+    int rows; // output rows per strip
+    Coef<R> c;
+    double b_thr, cx, cy; // envelope diagnostics (DIAG only)
+};
+
+struct DiagAcc {
+    double sb, sn, m2;
+};
+
+template <typename R, int T, int LAW, int PF, bool DIAG>
+__device__ __forceinline__ void stream_strip(const StripArgs<R> &a, int sx, int sy, DiagAcc &acc)
+{
+    constexpr int VEC = StreamShape<R>::VEC;
+    constexpr int HX = Halo<T, VEC>::HX;
+    constexpr int WC = Halo<T, VEC>::WC;
+    constexpr int OW = Halo<T, VEC>::OW;
+    typedef typename VecT<R, VEC>::type vec_t;
+
+    const int lane = threadIdx.x & 63;
+    const int x0 = sx * OW - HX + lane * VEC; // first column of this lane
+    const int y0 = sy * a.rows;
+    const int y1 = min(y0 + a.rows, a.ny);
+    const int rs = max(y0 - T, 0); // first input row
+    const int re = y1 + T;         // one past the last input row needed
+    const bool lane_in = (x0 >= 0) && (x0 < a.pitch);
+    const bool lane_out = (lane * VEC >= HX) && (lane * VEC < WC - HX) && (x0 < a.nx);
+    bool ve[VEC]; // east face of cell k is interior
+#pragma unroll
+    for (int k = 0; k < VEC; ++k)
+        ve[k] = (x0 + k >= 0) && (x0 + k + 1 < a.nx);
+
+    // level state: centre row of level L and the face inflow G(S,P) below it
+    R cb[T][VEC], cn[T][VEC], cD[T][VEC], cX[T][VEC], cs[T][VEC], fb[T][VEC], fn[T][VEC];
+#pragma unroll
+    for (int L = 0; L < T; ++L)
+#pragma unroll
+        for (int k = 0; k < VEC; ++k)
+            cb[L][k] = cn[L][k] = cD[L][k] = cX[L][k] = cs[L][k] = fb[L][k] = fn[L][k] = R(0);
+
+    // prefetch ring: slot (row - rs) % PF
+    vec_t pb[PF], pn[PF], ps[PF];
+    const vec_t zero = (vec_t)(R(0));
+#pragma unroll
+    for (int u = 0; u < PF; ++u) {
+        const int row = rs + u;
+        if (row < a.ny && lane_in) {
+            const size_t p = (size_t)row * a.pitch + x0;
+            pb[u] = *reinterpret_cast<const vec_t *>(a.b_in + p);
+            pn[u] = *reinterpret_cast<const vec_t *>(a.n_in + p);
+            ps[u] = *reinterpret_cast<const vec_t *>(a.sg + p);
+        } else {
+            pb[u] = pn[u] = ps[u] = zero;
+        }
+    }
+
+    for (int r0 = rs; r0 < re; r0 += PF) {
+#pragma unroll
+        for (int u = 0; u < PF; ++u) {
+            const int row = r0 + u;
+            // consume slot u (row), refill it with row + PF
+            R ib[VEC], in[VEC], iD[VEC], iX[VEC], is[VEC];
+#pragma unroll
+            for (int k = 0; k < VEC; ++k) {
+                ib[k] = pb[u][k];
+                in[k] = pn[u][k];
+                is[k] = R(0.5) * ps[u][k];
+            }
+            {
+                const int nrow = row + PF;
+                if (nrow < re && nrow < a.ny && lane_in) {
+                    const size_t p = (size_t)nrow * a.pitch + x0;
+                    pb[u] = *reinterpret_cast<const vec_t *>(a.b_in + p);
+                    pn[u] = *reinterpret_cast<const vec_t *>(a.n_in + p);
+                    ps[u] = *reinterpret_cast<const vec_t *>(a.sg + p);
+                } else {
+                    pb[u] = pn[u] = ps[u] = zero;
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < VEC; ++k)
+                coef<R, LAW>(is[k], in[k], ib[k], a.c.chi2, iD[k], iX[k]);
+
+#pragma unroll
+            for (int L = 0; L < T; ++L) {
+                const int y = row - L - 1; // centre row of this level
+                const bool vv = (y >= 0) && (y + 1 < a.ny);
+                R gvb[VEC], gvn[VEC], geb[VEC], gen[VEC];
+#pragma unroll
+                for (int k = 0; k < VEC; ++k)
+                    face<R>(cb[L][k], cn[L][k], cD[L][k], cX[L][k], ib[k], in[k], iD[k], iX[k], vv,
+                            gvb[k], gvn[k]);
+#pragma unroll
+                for (int k = 0; k + 1 < VEC; ++k)
+                    face<R>(cb[L][k], cn[L][k], cD[L][k], cX[L][k], cb[L][k + 1], cn[L][k + 1],
+                            cD[L][k + 1], cX[L][k + 1], ve[k], geb[k], gen[k]);
+                {
+                    const R eb = from_next(cb[L][0]), en = from_next(cn[L][0]);
+                    const R eD = from_next(cD[L][0]), eX = from_next(cX[L][0]);
+                    face<R>(cb[L][VEC - 1], cn[L][VEC - 1], cD[L][VEC - 1], cX[L][VEC - 1], eb, en,
+                            eD, eX, ve[VEC - 1], geb[VEC - 1], gen[VEC - 1]);
+                }
+                const R wb = from_prev(geb[VEC - 1]), wn = from_prev(gen[VEC - 1]);
+                R ob[VEC], on[VEC], os[VEC];
+#pragma unroll
+                for (int k = 0; k < VEC; ++k) {
+                    const R Fb = net<R>(geb[k], k ? geb[k - 1] : wb, gvb[k], fb[L][k]);
+                    const R Fn = net<R>(gen[k], k ? gen[k - 1] : wn, gvn[k], fn[L][k]);
+                    update<R>(cb[L][k], cn[L][k], Fb, Fn, a.c, ob[k], on[k]);
+                    os[k] = cs[L][k];
+                }
+#pragma unroll
+                for (int k = 0; k < VEC; ++k) {
+                    fb[L][k] = gvb[k];
+                    fn[L][k] = gvn[k];
+                    cb[L][k] = ib[k];
+                    cn[L][k] = in[k];
+                    cD[L][k] = iD[k];
+                    cX[L][k] = iX[k];
+                    cs[L][k] = is[k];
+                }
+                if (L + 1 < T) {
+#pragma unroll
+                    for (int k = 0; k < VEC; ++k) {
+                        ib[k] = ob[k];
+                        in[k] = on[k];
+                        is[k] = os[k];
+                        coef<R, LAW>(is[k], in[k], ib[k], a.c.chi2, iD[k], iX[k]);
+                    }
+                } else if (y >= y0 && y < y1 && lane_out) {
+                    vec_t vb, vn;
+#pragma unroll
+                    for (int k = 0; k < VEC; ++k) {
+                        vb[k] = ob[k];
+                        vn[k] = on[k];
+                    }
+                    const size_t p = (size_t)y * a.pitch + x0;
+                    *reinterpret_cast<vec_t *>(a.b_out + p) = vb;
+                    *reinterpret_cast<vec_t *>(a.n_out + p) = vn;
+                    if (DIAG) {
+                        const double dy = (double)y - a.cy;
+#pragma unroll
+                        for (int k = 0; k < VEC; ++k) {
+                            if (x0 + k < a.nx) {
+                                const double bv = (double)ob[k];
+                                acc.sb += bv;
+                                acc.sn += (double)on[k];
+                                if (bv >= a.b_thr) {
+                                    const double dx = (double)(x0 + k) - a.cx;
+                                    acc.m2 = fmax(acc.m2, dx * dx + dy * dy);
+                                }
+                            }
+                        }
+                    }
+                }
+            }
+        }
+    }
+}
+
+// Butterfly reductions over the 64 lanes of a wavefront (fixed order).
+__device__ __forceinline__ double wave_sum64(double v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1)
+        v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ double wave_max64(double v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1)
+        v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+} // namespace kc

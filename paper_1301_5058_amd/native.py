@@ -30,6 +30,12 @@ class KcParams(ctypes.Structure):
                 ("cx", c_double), ("cy", c_double), ("step0", c_int64)]
 
 
+class KbInstance(ctypes.Structure):
+    _fields_ = [("nx", c_int32), ("ny", c_int32), ("h", c_double), ("dt", c_double),
+                ("D_n", c_double), ("theta", c_double), ("kappa", c_double), ("chi", c_double),
+                ("b_thr", c_double), ("cx", c_double), ("cy", c_double)]
+
+
 class KcError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__("%s (status %d)" % (msg, code))
@@ -57,6 +63,21 @@ _SIGS = {
     "kc_destroy": (None, [c_void_p]),
     "kc_strerror": (ctypes.c_char_p, [c_int32]),
     "kc_last_error": (ctypes.c_char_p, [c_void_p]),
+    # batch (kb.h)
+    "kb_create": (c_int32, [c_int32, ctypes.POINTER(KbInstance), c_int32, c_int32, c_void_p,
+                            ctypes.POINTER(c_void_p)]),
+    "kb_set_fields": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_int32]),
+    "kb_run": (c_int32, [c_void_p, c_int64, c_int32]),
+    "kb_series": (c_int32, [c_void_p, c_void_p, ctypes.POINTER(c_int32), c_int32]),
+    "kb_get_fields": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_int32]),
+    "kb_fit_velocity": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "kb_set_tuning": (c_int32, [c_void_p, c_int32, c_void_p, c_int32, c_int32]),
+    "kb_get_tuning": (c_int32, [c_void_p, ctypes.POINTER(c_int32), c_void_p,
+                                ctypes.POINTER(c_int32), ctypes.POINTER(c_int32)]),
+    "kb_set_spin_limit": (c_int32, [c_void_p, c_int64]),
+    "kb_steps": (c_int32, [c_void_p, ctypes.POINTER(c_int64)]),
+    "kb_destroy": (None, [c_void_p]),
+    "kb_last_error": (ctypes.c_char_p, [c_void_p]),
 }
 
 _lib = None
@@ -78,11 +99,13 @@ def lib():
     return _lib
 
 
-def check(code, ctx=None):
-    """Raise KcError for a negative status."""
+def check(code, ctx=None, kind="kc"):
+    """Raise KcError for a negative status (message from the kc or kb handle)."""
     if code != KC_OK:
         L = lib()
-        msg = L.kc_last_error(ctx).decode() if ctx else ""
+        msg = ""
+        if ctx:
+            msg = (L.kc_last_error(ctx) if kind == "kc" else L.kb_last_error(ctx)).decode()
         raise KcError(code, msg or L.kc_strerror(code).decode())
     return code
 

@@ -131,3 +131,38 @@ def test_suggest_dt():
     assert L.kc_suggest_dt(1.0, 1.0, 0.3) == pytest.approx(0.2)
     assert L.kc_suggest_dt(0.5, 1.0, 2.0) == pytest.approx(0.2 * 0.25 / 2.0)
     assert L.kc_suggest_dt(0.0, 1.0, 1.0) == 0.0
+
+
+def _kb_create(count=2, law=0, cap=10, **kw):
+    L = N.lib()
+    arr = (N.KbInstance * max(count, 1))()
+    for k in range(max(count, 1)):
+        I = arr[k]
+        I.nx, I.ny, I.h, I.dt = 32, 32, 1.0, 0.1
+        I.D_n = I.theta = I.kappa = 1.0
+        I.chi, I.b_thr, I.cx, I.cy = 0.5, 0.4, math.nan, math.nan
+        for key, v in kw.items():
+            setattr(I, key, v)
+    h = ctypes.c_void_p()
+    rc = L.kb_create(count, arr, law, cap, None, ctypes.byref(h))
+    if rc == N.KC_OK:
+        L.kb_destroy(h)
+    return rc, h
+
+
+@pytest.mark.parametrize("args", [dict(count=0), dict(law=5), dict(cap=0), dict(nx=0),
+                                  dict(dt=-1.0), dict(h=math.inf), dict(chi=-1.0),
+                                  dict(kappa=math.nan), dict(ny=1 << 17), dict(b_thr=math.nan)])
+def test_batch_create_rejects_bad_arguments(args):
+    rc, h = _kb_create(**args)
+    assert rc == N.KC_EINVAL and not h.value
+
+
+def test_batch_null_handles():
+    L = N.lib()
+    L.kb_destroy(None)
+    assert L.kb_run(None, 10, 10) == N.KC_EINVAL
+    assert L.kb_set_fields(None, 0, None, None, None, 0) == N.KC_EINVAL
+    assert L.kb_series(None, None, None, 0) == N.KC_EINVAL
+    assert L.kb_set_spin_limit(None, 5) == N.KC_EINVAL
+    assert L.kb_last_error(None) == b"null batch"

@@ -1,0 +1,155 @@
+"""Batched sweep (kb_*) on the GPU: every instance of a batch must reproduce
+the single-instance solver bit for bit, the device-side samples must equal
+the single-instance diagnostics, the persistent launch must equal one launch
+per time block, and the velocity fit must equal the oracle's fit of the same
+series."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1301_5058_amd import workload
+
+pytestmark = pytest.mark.gpu
+
+INSTANCES = [
+    dict(nx=64, ny=64, n0=0.8, a=0.5, chi=0.5, seed=1),
+    dict(nx=100, ny=77, n0=1.1, a=0.2, chi=1.7, seed=2),
+    dict(nx=300, ny=130, n0=0.4, a=0.4, chi=0.0, seed=3),
+    dict(nx=1, ny=50, n0=0.9, a=0.3, chi=1.0, seed=4),
+    dict(nx=257, ny=256, n0=0.6, a=0.1, chi=2.0, seed=5),
+    dict(nx=33, ny=3, n0=0.7, a=0.5, chi=0.3, seed=6),
+]
+
+
+def _setup(insts, law="receptor", **kw):
+    from paper_1301_5058_amd.batch import Batch
+    fields, descs = [], []
+    for d in insts:
+        b, n, s = workload.fields(d["nx"], d["ny"], d["n0"], d["a"], d["seed"],
+                                  r0=max(1.0, min(6.0, min(d["nx"], d["ny"]) / 6.0)))
+        dt = workload.config_dt(b, n, s)
+        fields.append((b, n, s))
+        descs.append(dict(nx=d["nx"], ny=d["ny"], dt=dt, chi=d["chi"], b_thr=0.5 * d["n0"]))
+    B = Batch(descs, chi_law=law, **kw)
+    for k, (b, n, s) in enumerate(fields):
+        B.set_fields(k, b, n, s)
+    return B, fields, descs
+
+
+def _single(b, n, s, desc, steps, every, law="receptor"):
+    from paper_1301_5058_amd.solver import Solver
+    S = Solver(desc["nx"], desc["ny"], dt=desc["dt"], chi=desc["chi"], chi_law=law,
+               b_thr=desc["b_thr"])
+    S.set_fields(b, n, s)
+    diags = []
+    for _ in range(steps // every):
+        S.step(every)
+        t, _k = S.time()
+        diags.append((t,) + S.diagnostics())
+    fb, fn = S.get_fields()
+    S.close()
+    return fb, fn, np.array(diags)
+
+
+@pytest.mark.parametrize("law", ["receptor", "constant"])
+def test_batch_matches_single_instance_bitwise(law):
+    steps, every = 120, 20
+    B, fields, descs = _setup(INSTANCES, law=law, max_samples=64)
+    B.run(steps, every)
+    ser = B.series()
+    assert ser.shape == (len(INSTANCES), steps // every, 4)
+    for k, ((b, n, s), d) in enumerate(zip(fields, descs)):
+        fb, fn, diags = _single(b, n, s, d, steps, every, law)
+        gb, gn = B.get_fields(k)
+        assert np.array_equal(gb, fb) and np.array_equal(gn, fn), k
+        assert np.array_equal(ser[k, :, 0], diags[:, 0])
+        np.testing.assert_allclose(ser[k, :, 1:3], diags[:, 1:3], rtol=1e-13, atol=0)
+        assert np.array_equal(ser[k, :, 3], diags[:, 3])
+    B.close()
+
+
+def test_persistent_equals_per_block_launches_and_any_tuning():
+    steps, every = 96, 24
+    ref = None
+    for tune in [dict(persistent=0, tsteps=1), dict(persistent=1, tsteps=2),
+                 dict(persistent=1, tsteps=4, rows=5, prefetch=2),
+                 dict(persistent=1, tsteps=8, rows=64), dict(persistent=0, tsteps=3, rows=7)]:
+        B, _, _ = _setup(INSTANCES, max_samples=16)
+        B.set_tuning(**tune)
+        B.run(steps // 2, every)
+        B.run(steps // 2, every)
+        got = (B.series(), [B.get_fields(k) for k in range(len(INSTANCES))])
+        assert B.steps() == steps
+        B.close()
+        if ref is None:
+            ref = got
+            continue
+        assert np.array_equal(got[0], ref[0]), tune
+        for (a, b_), (c, d) in zip(got[1], ref[1]):
+            assert np.array_equal(a, c) and np.array_equal(b_, d), tune
+
+
+def test_instance_matches_oracle():
+    d = INSTANCES[1]
+    B, fields, descs = _setup([d], max_samples=8)
+    B.run(400, 100)
+    gb, gn = B.get_fields(0)
+    b, n, s = fields[0]
+    ob, on = oracle.run(b, n, s, 1.0, descs[0]["dt"], 400, chi=d["chi"])
+    assert np.max(np.abs(gb - ob)) / np.max(ob) <= 1e-4
+    assert np.max(np.abs(gn - on)) / np.max(on) <= 1e-4
+    m, nu, r = oracle.diag(ob, on, 1.0, descs[0]["b_thr"])
+    ser = B.series()
+    assert abs(ser[0, -1, 1] - m) / m <= 5e-3 and abs(ser[0, -1, 3] - r) <= max(1.0, 5e-3 * r)
+    B.close()
+
+
+def test_velocity_fit_equals_oracle_fit_of_same_series():
+    insts = [dict(nx=160, ny=160, n0=0.9, a=0.3, chi=c, seed=k) for k, c in enumerate((0.0, 2.0))]
+    B, _, _ = _setup(insts, max_samples=64)
+    B.run(3000, 100)
+    ser = B.series()
+    lo, hi = np.array([8.0, 8.0]), np.array([60.0, 60.0])
+    v, npts = B.fit_velocity(lo, hi)
+    for k in range(2):
+        vo, ko = oracle.fit_velocity(ser[k, :, 0], ser[k, :, 3], lo[k], hi[k])
+        assert npts[k] == ko and ko >= 3
+        assert v[k] == pytest.approx(vo, rel=1e-12)
+    # chemotaxis speeds the envelope up (abstract; Sec. 3.1; Sec. 4.1 eq. speedinq)
+    assert v[1] > v[0] > 0
+    v2, n2 = B.fit_velocity(1e6, 2e6)
+    assert np.all(np.isnan(v2)) and np.all(n2 == 0)
+    B.close()
+
+
+def test_error_paths_and_bounded_wait():
+    from paper_1301_5058_amd import native as N
+    from paper_1301_5058_amd.batch import Batch
+    B = Batch([dict(nx=512, ny=512, dt=0.2, chi=0.5, b_thr=0.4)], max_samples=4)
+    with pytest.raises(N.KcError) as e:
+        B.run(10, 10)
+    assert e.value.code == N.KC_ESTATE
+    b, n, s = workload.fields(512, 512, 0.8, 0.5, 0)
+    B.set_fields(0, b, n, s)
+    with pytest.raises(N.KcError) as e:
+        B.run(15, 10)
+    assert e.value.code == N.KC_EINVAL
+    with pytest.raises(N.KcError) as e:
+        B.run(50, 10)  # 5 samples > capacity 4
+    assert e.value.code == N.KC_EINVAL
+    # a one-poll bound on the persistent kernel's waits: items of the second
+    # time block are handed out while the first block is still running, so a
+    # wait cannot be satisfied at its first poll and the launch stops cleanly
+    B.set_tuning(tsteps=1, rows=8, persistent=1)
+    B.set_spin_limit(1)
+    with pytest.raises(N.KcError) as e:
+        B.run(40, 10)
+    assert e.value.code == N.KC_EHIP
+    B.set_spin_limit(1 << 23)
+    B.set_fields(0, b, n, s)
+    B.run(40, 10)
+    assert B.nsamples() == 4
+    B.close()
