@@ -91,6 +91,15 @@ int kb_set_tuning(kb_batch *bt, int32_t tsteps, const int32_t *rows, int32_t pre
 int kb_get_tuning(const kb_batch *bt, int32_t *tsteps, int32_t *rows, int32_t *prefetch,
                   int32_t *persistent);
 
+/* Pick the time-block depth (a compiled depth dividing sample_every), the
+ * prefetch depth and every instance's strip height by timing fused
+ * single-instance launches on one instance of each distinct grid shape
+ * (current level in, scratch level out: the state is unchanged), then taking
+ * the depth and prefetch with the least total estimated time over all
+ * instances.  effort as kc_autotune.  Requires fields on every instance.
+ * Synchronous. */
+int kb_autotune(kb_batch *bt, int32_t effort, int32_t sample_every);
+
 /* Bound of each wait of the persistent kernel, in polls (default 2^23, a few
  * seconds).  A tiny bound makes a run stop early with KC_EHIP. */
 int kb_set_spin_limit(kb_batch *bt, int64_t polls);

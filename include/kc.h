@@ -131,6 +131,17 @@ int kc_check_fields(int32_t nx, int32_t ny, int precision, const void *b0, const
 int kc_set_tuning(kc_ctx *ctx, int32_t tsteps, int32_t rows, int32_t prefetch);
 int kc_get_tuning(const kc_ctx *ctx, int32_t *tsteps, int32_t *rows, int32_t *prefetch);
 
+/* Pick the fused-kernel configuration (as kc_set_tuning) by timing candidate
+ * launches on the context's own fields: each launch reads the current level
+ * and writes the scratch level, so the state is unchanged.  effort 0 tries 16
+ * candidates, 1 the full grid of 120.  With use_cache != 0 a matching entry
+ * of the file named by the environment variable KC_AUTOTUNE_CACHE (one JSON
+ * object per line, keyed by device, grid, precision and law) is used instead
+ * of timing, and a new result is appended to it.  *gcell_s (may be NULL)
+ * receives the best measured rate in 1e9 cell-updates/s (0 when the cache
+ * answered).  Requires fields (KC_ESTATE).  Synchronous. */
+int kc_autotune(kc_ctx *ctx, int32_t effort, int32_t use_cache, double *gcell_s);
+
 /* Use the one-step-per-launch global-memory kernel (1) or the fused,
  * register-streaming kernel (0, default).  Both give bitwise equal fields. */
 int kc_set_reference_kernel(kc_ctx *ctx, int32_t on);

@@ -115,6 +115,9 @@ class Batch:
                                         ctypes.byref(p), ctypes.byref(q)))
         return t.value, rows, p.value, q.value
 
+    def autotune(self, sample_every, effort=0):
+        self._chk(N.lib().kb_autotune(self.h, int(effort), int(sample_every)))
+
     def set_spin_limit(self, polls):
         self._chk(N.lib().kb_set_spin_limit(self.h, int(polls)))
 

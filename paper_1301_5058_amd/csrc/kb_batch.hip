@@ -786,6 +786,97 @@ int kb_get_tuning(const kb_batch *b, int32_t *tsteps, int32_t *rows, int32_t *pr
     return KC_OK;
 }
 
+int kb_autotune(kb_batch *b, int32_t effort, int32_t sample_every)
+{
+    if (!b)
+        return KC_EINVAL;
+    b->err.clear();
+    if (effort < 0 || effort > 1 || sample_every < 1)
+        return bfail(b, KC_EINVAL, "bad autotune arguments");
+    for (int k = 0; k < b->count; ++k)
+        if (!b->has_fields[k])
+            return bfail(b, KC_ESTATE, "instance %d has no fields", k);
+    kc::Tuning cand[256];
+    int n = 0;
+    kc::tuning_candidates(effort, 8, cand, &n, 256);
+    // distinct shapes and the instances that use them
+    std::vector<std::pair<int, int>> shapes;
+    std::vector<int> shape_of(b->count), rep;
+    for (int k = 0; k < b->count; ++k) {
+        const std::pair<int, int> sh(b->inst[k].nx, b->inst[k].ny);
+        int idx = -1;
+        for (size_t i = 0; i < shapes.size(); ++i)
+            if (shapes[i] == sh)
+                idx = (int)i;
+        if (idx < 0) {
+            idx = (int)shapes.size();
+            shapes.push_back(sh);
+            rep.push_back(k);
+        }
+        shape_of[k] = idx;
+    }
+    // per shape, per (T, prefetch): best rows and its time per step
+    const int depths[] = {1, 2, 3, 4, 6, 8};
+    const int nd = 6;
+    std::vector<double> best_ms(shapes.size() * nd * 2, 1e300);
+    std::vector<int> best_rows(shapes.size() * nd * 2, 32);
+    for (size_t si = 0; si < shapes.size(); ++si) {
+        const BInst &H = b->hinst[rep[si]];
+        kc::Fields<float> f;
+        f.b_in = H.b[b->cur];
+        f.n_in = H.n[b->cur];
+        f.sg = H.sg;
+        f.b_out = H.b[b->cur ^ 1];
+        f.n_out = H.n[b->cur ^ 1];
+        f.nx = H.nx;
+        f.ny = H.ny;
+        f.pitch = H.pitch;
+        const double cells = (double)H.nx * H.ny;
+        for (int i = 0; i < n; ++i) {
+            if (sample_every % cand[i].tsteps != 0)
+                continue;
+            int reps = (int)(2e8 / (cells * cand[i].tsteps));
+            reps = reps < 2 ? 2 : reps > 20 ? 20 : reps;
+            double ms = 0;
+            KB_HIP(b, kc::time_stream<float>(f, H.c, b->law, cand[i], b->stream, reps, &ms));
+            int di = 0;
+            while (depths[di] != cand[i].tsteps)
+                ++di;
+            const size_t slot = (si * nd + di) * 2 + (cand[i].prefetch == 4 ? 1 : 0);
+            const double per_step = ms / cand[i].tsteps;
+            if (per_step < best_ms[slot]) {
+                best_ms[slot] = per_step;
+                best_rows[slot] = cand[i].rows;
+            }
+        }
+    }
+    // count instances per shape, then the (T, prefetch) with least total time
+    std::vector<int> mult(shapes.size(), 0);
+    for (int k = 0; k < b->count; ++k)
+        ++mult[shape_of[k]];
+    double best_total = 1e300;
+    int bdi = -1, bpf = 1;
+    for (int di = 0; di < nd; ++di)
+        for (int pf = 0; pf < 2; ++pf) {
+            double tot = 0;
+            for (size_t si = 0; si < shapes.size(); ++si)
+                tot += mult[si] * best_ms[(si * nd + di) * 2 + pf];
+            if (tot < best_total) {
+                best_total = tot;
+                bdi = di;
+                bpf = pf;
+            }
+        }
+    if (bdi < 0 || best_total >= 1e299)
+        return bfail(b, KC_EINVAL, "no compiled depth divides sample_every = %d", sample_every);
+    b->T = depths[bdi];
+    b->pf = bpf ? 4 : 2;
+    for (int k = 0; k < b->count; ++k)
+        b->rows[k] = best_rows[(shape_of[k] * nd + bdi) * 2 + bpf];
+    b->geom_dirty = true;
+    return KC_OK;
+}
+
 int kb_set_spin_limit(kb_batch *b, int64_t polls)
 {
     if (!b || polls < 1)

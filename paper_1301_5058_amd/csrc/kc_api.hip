@@ -169,6 +169,34 @@ bool sizes_ok(int nx, int ny)
            (double)kc::pitch_for(nx) * (double)ny < 4.0e9;
 }
 
+template <typename R> int autotune_impl(kc_ctx *c, int effort, double *best_out)
+{
+    const Coef<R> k = make_coef<R>(c);
+    const Fields<R> f = make_fields<R>(c); // current level in, scratch level out
+    kc::Tuning cand[256];
+    int n = 0;
+    kc::tuning_candidates(effort, 8, cand, &n, 256);
+    const double cells = (double)c->nx * c->ny;
+    double best = 1e300;
+    kc::Tuning bt = c->tune;
+    for (int i = 0; i < n; ++i) {
+        int reps = (int)(4e8 / (cells * cand[i].tsteps));
+        reps = reps < 2 ? 2 : reps > 20 ? 20 : reps;
+        double ms = 0;
+        hipError_t e = kc::time_stream<R>(f, k, c->p.chi_law, cand[i], c->stream, reps, &ms);
+        if (e != hipSuccess)
+            return hipfail(c, e, "autotune launch");
+        const double per_step = ms / cand[i].tsteps;
+        if (per_step < best) {
+            best = per_step;
+            bt = cand[i];
+        }
+    }
+    c->tune = bt;
+    *best_out = cells / (best * 1e-3) / 1e9;
+    return KC_OK;
+}
+
 } // namespace
 
 extern "C" {
@@ -486,6 +514,36 @@ int kc_get_tuning(const kc_ctx *c, int32_t *tsteps, int32_t *rows, int32_t *pref
         *rows = c->tune.rows;
     if (prefetch)
         *prefetch = c->tune.prefetch;
+    return KC_OK;
+}
+
+int kc_autotune(kc_ctx *c, int32_t effort, int32_t use_cache, double *gcell_s)
+{
+    if (!c)
+        return KC_EINVAL;
+    c->err.clear();
+    if (effort < 0 || effort > 1)
+        return fail(c, KC_EINVAL, "effort must be 0 or 1");
+    if (!c->has_fields)
+        return fail(c, KC_ESTATE, "kc_autotune before kc_set_fields");
+    char key[256];
+    kc::device_key(key, sizeof key, c->nx, c->ny, c->p.precision, c->p.chi_law);
+    if (gcell_s)
+        *gcell_s = 0.0;
+    kc::Tuning t;
+    if (use_cache && kc::cache_lookup(key, &t)) {
+        c->tune = t;
+        return KC_OK;
+    }
+    double g = 0.0;
+    const int rc = c->p.precision == KC_FP32 ? autotune_impl<float>(c, effort, &g)
+                                             : autotune_impl<double>(c, effort, &g);
+    if (rc != KC_OK)
+        return rc;
+    if (use_cache)
+        kc::cache_store(key, c->tune, g);
+    if (gcell_s)
+        *gcell_s = g;
     return KC_OK;
 }
 

@@ -43,6 +43,23 @@ hipError_t launch_stream(const Fields<R> &f, const Coef<R> &c, int chi_law, cons
 template <typename R>
 hipError_t launch_ref(const Fields<R> &f, const Coef<R> &c, int chi_law, hipStream_t s);
 
+// Average duration (ms) of one fused launch with tuning t, from `reps` launches
+// after one warm-up launch, timed with HIP events on stream s.  The launch
+// reads f's input level and writes its output level; nothing else changes.
+template <typename R>
+hipError_t time_stream(const Fields<R> &f, const Coef<R> &c, int chi_law, const Tuning &t,
+                       hipStream_t s, int reps, double *ms);
+
+// Candidate configurations of the autotuner: effort 0 is a short list, 1 the
+// full grid (tsteps in {1,2,3,4,6,8}, rows in 8..256, prefetch 2 or 4).
+void tuning_candidates(int effort, int max_tsteps, Tuning *out, int *n, int cap);
+
+// Autotune cache: one JSON object per line, keyed by device, grid, precision
+// and sensitivity law.  Path from KC_AUTOTUNE_CACHE, else none.
+bool cache_lookup(const char *key, Tuning *t);
+void cache_store(const char *key, const Tuning &t, double gcells);
+int device_key(char *buf, size_t n, int nx, int ny, int precision, int chi_law);
+
 // Diagnostics: partial sums over row blocks, then one fixed-order final pass
 // writing {t, mass, nutrient, radius} to out4 (device doubles).
 int diag_parts(int ny);

@@ -190,6 +190,68 @@ hipError_t launch_ref(const Fields<R> &f, const Coef<R> &c, int chi_law, hipStre
     return hipGetLastError();
 }
 
+template <typename R>
+hipError_t time_stream(const Fields<R> &f, const Coef<R> &c, int chi_law, const Tuning &t,
+                       hipStream_t s, int reps, double *ms)
+{
+    hipEvent_t e0, e1;
+    hipError_t e = hipEventCreate(&e0);
+    if (e != hipSuccess)
+        return e;
+    e = hipEventCreate(&e1);
+    if (e != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return e;
+    }
+    e = launch_stream<R>(f, c, chi_law, t, s);
+    if (e == hipSuccess)
+        e = hipEventRecord(e0, s);
+    for (int i = 0; i < reps && e == hipSuccess; ++i)
+        e = launch_stream<R>(f, c, chi_law, t, s);
+    if (e == hipSuccess)
+        e = hipEventRecord(e1, s);
+    if (e == hipSuccess)
+        e = hipEventSynchronize(e1);
+    float el = 0.f;
+    if (e == hipSuccess)
+        e = hipEventElapsedTime(&el, e0, e1);
+    if (e == hipSuccess)
+        *ms = (double)el / reps;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return e;
+}
+
+void tuning_candidates(int effort, int max_tsteps, Tuning *out, int *n, int cap)
+{
+    static const int quick_t[] = {1, 2, 3, 4};
+    static const int quick_r[] = {16, 32, 64, 128};
+    static const int full_t[] = {1, 2, 3, 4, 6, 8};
+    static const int full_r[] = {8, 12, 16, 24, 32, 48, 64, 96, 128, 256};
+    const int *ts = effort ? full_t : quick_t;
+    const int *rs = effort ? full_r : quick_r;
+    const int nt = effort ? 6 : 4, nr = effort ? 10 : 4;
+    int k = 0;
+    for (int i = 0; i < nt; ++i) {
+        if (ts[i] > max_tsteps)
+            continue;
+        for (int j = 0; j < nr; ++j)
+            for (int p = 0; p < (effort ? 2 : 1); ++p) {
+                if (k < cap) {
+                    out[k].tsteps = ts[i];
+                    out[k].rows = rs[j];
+                    out[k].prefetch = p ? 2 : 4;
+                }
+                ++k;
+            }
+    }
+    *n = k < cap ? k : cap;
+}
+
+template hipError_t time_stream<float>(const Fields<float> &, const Coef<float> &, int,
+                                       const Tuning &, hipStream_t, int, double *);
+template hipError_t time_stream<double>(const Fields<double> &, const Coef<double> &, int,
+                                        const Tuning &, hipStream_t, int, double *);
 template hipError_t launch_stream<float>(const Fields<float> &, const Coef<float> &, int,
                                          const Tuning &, hipStream_t);
 template hipError_t launch_stream<double>(const Fields<double> &, const Coef<double> &, int,

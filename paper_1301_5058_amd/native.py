@@ -60,6 +60,7 @@ _SIGS = {
     "kc_get_tuning": (c_int32, [c_void_p, ctypes.POINTER(c_int32), ctypes.POINTER(c_int32),
                                 ctypes.POINTER(c_int32)]),
     "kc_set_reference_kernel": (c_int32, [c_void_p, c_int32]),
+    "kc_autotune": (c_int32, [c_void_p, c_int32, c_int32, P_double]),
     "kc_destroy": (None, [c_void_p]),
     "kc_strerror": (ctypes.c_char_p, [c_int32]),
     "kc_last_error": (ctypes.c_char_p, [c_void_p]),
@@ -75,6 +76,7 @@ _SIGS = {
     "kb_get_tuning": (c_int32, [c_void_p, ctypes.POINTER(c_int32), c_void_p,
                                 ctypes.POINTER(c_int32), ctypes.POINTER(c_int32)]),
     "kb_set_spin_limit": (c_int32, [c_void_p, c_int64]),
+    "kb_autotune": (c_int32, [c_void_p, c_int32, c_int32]),
     "kb_steps": (c_int32, [c_void_p, ctypes.POINTER(c_int64)]),
     "kb_destroy": (None, [c_void_p]),
     "kb_last_error": (ctypes.c_char_p, [c_void_p]),

@@ -110,6 +110,14 @@ class Solver:
         N.check(N.lib().kc_get_tuning(self.ctx, ctypes.byref(t), ctypes.byref(r), ctypes.byref(p)))
         return t.value, r.value, p.value
 
+    def autotune(self, effort=0, use_cache=True):
+        """Time candidate kernel configurations on this solver's fields and keep
+        the fastest; returns its rate in 1e9 cell-updates/s (0 if cached)."""
+        g = ctypes.c_double()
+        N.check(N.lib().kc_autotune(self.ctx, int(effort), 1 if use_cache else 0, ctypes.byref(g)),
+                self.ctx)
+        return g.value
+
     def use_reference_kernel(self, on=True):
         N.check(N.lib().kc_set_reference_kernel(self.ctx, 1 if on else 0), self.ctx)
 

@@ -153,3 +153,21 @@ def test_error_paths_and_bounded_wait():
     B.run(40, 10)
     assert B.nsamples() == 4
     B.close()
+
+
+def test_batch_autotune_keeps_results():
+    steps, every = 60, 20
+    B0, _, _ = _setup(INSTANCES, max_samples=8)
+    B0.run(steps, every)
+    ref = (B0.series(), [B0.get_fields(k) for k in range(len(INSTANCES))])
+    B0.close()
+    B, _, _ = _setup(INSTANCES, max_samples=8)
+    B.autotune(every, effort=0)
+    T, rows, pf, _p = B.tuning()
+    assert every % T == 0 and np.all(rows >= 1) and pf in (2, 4)
+    B.run(steps, every)
+    assert np.array_equal(B.series(), ref[0])
+    for k in range(len(INSTANCES)):
+        gb, gn = B.get_fields(k)
+        assert np.array_equal(gb, ref[1][k][0]) and np.array_equal(gn, ref[1][k][1])
+    B.close()

@@ -259,3 +259,32 @@ def test_full_size_sampled_cells_match_oracle(cfg, launches):
         worst = max(worst, abs(gb[j, i] - eb), abs(gn[j, i] - en))
     print("%dx%d, %d steps (T=%d): worst sampled abs error %.3e" % (nx, ny, steps, T, worst))
     assert worst <= 2e-6
+
+
+# ----------------------------------------------------------------------------
+# Autotuner: picks a valid configuration, leaves the state alone, uses its cache
+# ----------------------------------------------------------------------------
+def test_autotune_keeps_state_and_caches(tmp_path, monkeypatch):
+    cache = tmp_path / "tune.jsonl"
+    monkeypatch.setenv("KC_AUTOTUNE_CACHE", str(cache))
+    b, n, s = workload.fields(520, 300, 0.8, 0.5, 3)
+    dt = workload.config_dt(b, n, s)
+    ref_b, ref_n, ref_d = run_gpu(b, n, s, 40, dt, chi=0.7)
+    S = _solver(520, 300, dt, chi=0.7)
+    S.set_fields(b, n, s)
+    S.step(1)
+    before = S.get_fields()
+    g = S.autotune(effort=0, use_cache=True)
+    assert g > 0
+    after = S.get_fields()
+    assert np.array_equal(before[0], after[0]) and np.array_equal(before[1], after[1])
+    t1 = S.tuning()
+    assert t1[0] in (1, 2, 3, 4) and t1[1] >= 1 and t1[2] in (2, 4)
+    S.step(39)
+    gb, gn = S.get_fields()
+    assert np.array_equal(gb, ref_b) and np.array_equal(gn, ref_n)
+    assert cache.read_text().count('"key"') == 1
+    S.set_tuning(1, 8, 2)
+    assert S.autotune(effort=0, use_cache=True) == 0.0  # answered by the cache
+    assert S.tuning() == t1
+    S.close()
