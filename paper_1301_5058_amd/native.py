@@ -80,6 +80,20 @@ _SIGS = {
     "kb_steps": (c_int32, [c_void_p, ctypes.POINTER(c_int64)]),
     "kb_destroy": (None, [c_void_p]),
     "kb_last_error": (ctypes.c_char_p, [c_void_p]),
+    # surrogate (ks.h)
+    "ks_create": (c_int32, [c_int32, c_void_p, ctypes.POINTER(c_void_p)]),
+    "ks_set_params": (c_int32, [c_void_p, c_void_p]),
+    "ks_get_params": (c_int32, [c_void_p, c_void_p]),
+    "ks_set_normalization": (c_int32, [c_void_p, c_void_p, c_void_p, c_double, c_double]),
+    "ks_train": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, c_int32, c_int32, c_double,
+                           c_int32, P_double]),
+    "ks_grad": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, c_void_p, P_double, c_int32]),
+    "ks_predict": (c_int32, [c_void_p, c_void_p, c_int32, c_void_p, c_int32]),
+    "ks_hull_set": (c_int32, [c_void_p, c_void_p, c_int32, c_double]),
+    "ks_hull_test": (c_int32, [c_void_p, c_void_p, c_int32, c_void_p, c_int32]),
+    "ks_cbar": (c_int32, [c_void_p, c_void_p, c_int32, c_double, c_void_p, c_int32]),
+    "ks_destroy": (None, [c_void_p]),
+    "ks_last_error": (ctypes.c_char_p, [c_void_p]),
 }
 
 _lib = None

@@ -1,0 +1,92 @@
+"""Surrogate MLP kernels (ks_*) against the FP64 reference network."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import mlp_ref
+
+pytestmark = pytest.mark.gpu
+
+MAPS = dict(in_shift=(0.75, 1.0, 0.3), in_scale=(0.45, 1.0, 0.2), out_shift=0.3, out_scale=0.2)
+
+
+def _model(maxp=70000, seed=0):
+    from paper_1301_5058_amd.surrogate import Surrogate, he_uniform
+    S = Surrogate(maxp)
+    S.set_normalization(MAPS["in_shift"], MAPS["in_scale"], MAPS["out_shift"], MAPS["out_scale"])
+    p = he_uniform(seed)
+    rng = np.random.default_rng(seed + 100)
+    p[192:256] = rng.uniform(-0.2, 0.2, 64)     # non-zero biases exercise every term
+    p[4352:4416] = rng.uniform(-0.2, 0.2, 64)
+    p[8512:8576] = rng.uniform(-0.2, 0.2, 64)
+    p[8640] = 0.1
+    S.set_params(p)
+    return S, p
+
+
+def _data(n, seed=1):
+    rng = np.random.default_rng(seed)
+    X = np.stack([rng.uniform(0.3, 1.2, n), rng.uniform(0, 2, n), rng.uniform(0.1, 0.5, n)],
+                 1).astype(np.float32)
+    y = (np.array([oracle.cbar(a, b) for a, b in X[:, :2].astype(np.float64)]) *
+         (1.0 + 0.1 * X[:, 2])).astype(np.float32)
+    return X, y
+
+
+@pytest.mark.parametrize("n", [1, 37, 1000, 4096])
+def test_gradient_matches_reference(n):
+    S, p = _model()
+    X, y = _data(n)
+    g, loss = S.grad(X, y)
+    lr, gr = mlp_ref.loss_and_grad(p.astype(np.float64), X.astype(np.float64), y, **MAPS)
+    assert loss == pytest.approx(lr, rel=2e-3)
+    for name, off, shape in mlp_ref.LAYOUT:
+        size = int(np.prod(shape)) if shape else 1
+        a, b = g[off:off + size].astype(np.float64), gr[off:off + size]
+        err = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+        print("%s rel err %.2e" % (name, err))
+        assert err <= 2e-2, name
+    S.close()
+
+
+def test_predict_matches_reference():
+    S, p = _model()
+    X, _ = _data(5003, 2)
+    v = S.predict(X)
+    vr, _ = mlp_ref.forward(p.astype(np.float64), X.astype(np.float64), **MAPS)
+    assert np.max(np.abs(v - vr)) <= 1e-2 * MAPS["out_scale"]
+    S.close()
+
+
+def test_training_fits_a_smooth_velocity_law():
+    S, _ = _model()
+    X, y = _data(4096, 3)
+    Xt, yt = _data(512, 4)
+    l0 = S.grad(X, y)[1]
+    loss = S.train(X, y, iters=3000, batch=1024, lr=2e-3)
+    assert loss < 0.02 * l0
+    rel = np.abs(S.predict(Xt) - yt) / yt
+    print("held-out median rel err %.4f, p95 %.4f" % (np.median(rel), np.quantile(rel, 0.95)))
+    assert np.median(rel) < 0.02
+    S.close()
+
+
+def test_hull_and_speed_bound_kernels():
+    from paper_1301_5058_amd.surrogate import hull_facets
+    S, _ = _model()
+    rng = np.random.default_rng(5)
+    pts = np.stack([rng.uniform(0.3, 1.2, 400), rng.uniform(0, 2, 400), rng.uniform(0.1, 0.5, 400)], 1)
+    F = hull_facets(pts)
+    S.set_hull(F, tol=1e-9)
+    Q = np.stack([rng.uniform(0.1, 1.5, 3000), rng.uniform(-0.5, 2.5, 3000),
+                  rng.uniform(0.0, 0.6, 3000)], 1).astype(np.float32)
+    d = Q.astype(np.float64) @ F[:, :3].T + F[:, 3]
+    want = np.all(d <= 1e-9, axis=1)
+    got = S.inside(Q)
+    clear = np.min(np.abs(d), axis=1) > 1e-6  # away from the facets
+    assert np.array_equal(got[clear], want[clear]) and want.any() and (~want).any()
+    cb = S.cbar(Q[:, :], sigma0=1.0)
+    ref = np.array([oracle.cbar(float(a), float(max(b, 0.0))) for a, b in Q[:, :2]])
+    ok = Q[:, 1] >= 0
+    np.testing.assert_allclose(cb[ok], ref[ok], rtol=2e-6)
+    S.close()
