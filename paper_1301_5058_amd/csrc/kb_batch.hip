@@ -89,16 +89,18 @@ __global__ __launch_bounds__(256) void batch_kernel(BatchArgs a)
         const int j = local - I.strip0;
 
         if (PERSIST && tau > 0) {
+            // poll with plain device-coherent loads; one acquire fence once satisfied
             const unsigned target = (unsigned)tau * (unsigned)I.nstrips;
             long long polls = 0;
-            while (__hip_atomic_load(&a.done[k], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) <
+            while (__hip_atomic_load(&a.done[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
                    target) {
                 if (++polls > a.spin_limit) {
                     __hip_atomic_store(a.abort_flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     return;
                 }
-                __builtin_amdgcn_s_sleep(4);
+                __builtin_amdgcn_s_sleep(8);
             }
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         }
 
         const int par = (a.parity0 + tau) & 1;
@@ -162,9 +164,9 @@ __global__ __launch_bounds__(256) void batch_kernel(BatchArgs a)
             }
         }
         if (PERSIST) {
-            __threadfence();
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); // this strip's stores first
             if (lane == 0)
-                __hip_atomic_fetch_add(&a.done[k], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_fetch_add(&a.done[k], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         } else {
             return;
         }
@@ -647,8 +649,10 @@ int kb_run(kb_batch *b, int64_t nsteps, int32_t sample_every)
         KB_HIP(b, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, 0));
         KB_HIP(b, hipGetDevice(&dev));
         KB_HIP(b, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        // no more wavefronts than one time block has strips: extra ones would only
+        // wait for the previous block
         long long g = (long long)(per_cu > 0 ? per_cu : 1) * cus;
-        const long long need = (a.total_items + 3) / 4;
+        const long long need = ((long long)b->S + 3) / 4;
         if (g > need)
             g = need;
         KB_HIP(b, dispatch(b->law, b->pf, true, T, a, dim3((unsigned)g), b->stream));
