@@ -5,8 +5,12 @@
 // instance k by T steps with stream_strip (kc_stream.h), so each instance
 // goes through the same per-cell arithmetic as the single-instance solver.
 //   PERSIST = true : one launch for the whole run; items come from a global
-//                    counter in tau-major order and an item of block tau first
-//                    waits (bounded) for done[k] >= tau * nstrips_k.
+//                    counter in tau-major order.  Strip j of block tau reads (and
+//                    overwrites the previous input of) only the strips of block
+//                    tau-1 whose output overlaps its halo window, so it waits
+//                    (bounded) until each of those has published progress
+//                    flag >= tau; it then publishes tau+1 for itself (release
+//                    fence, then a device-scope atomic store).
 //   PERSIST = false: one launch per time block, item = wavefront index.
 // On a sampling block each strip also folds the cells it stores into double
 // partials; the last strip of the instance to arrive (arrive[k] counter) sums
@@ -47,7 +51,9 @@ struct BatchArgs {
     int cap;               // samples per instance in the series
     long long step_base;   // steps done before this run
     unsigned long long *next;
-    unsigned *done, *arrive, *abort_flag;
+    unsigned *flags;  // [S] progress of every strip: blocks completed
+    unsigned *fin;    // [count] samples of this run already reduced
+    unsigned *arrive, *abort_flag;
     double *partials; // [S][3]
     double *series;   // [count][cap][4]
     long long spin_limit;
@@ -89,17 +95,30 @@ __global__ __launch_bounds__(256) void batch_kernel(BatchArgs a)
         const int j = local - I.strip0;
 
         if (PERSIST && tau > 0) {
-            // poll with plain device-coherent loads; one acquire fence once satisfied
-            const unsigned target = (unsigned)tau * (unsigned)I.nstrips;
+            // strips of block tau-1 whose output rows/columns meet this strip's
+            // input window [y0 - T, y1 + T) x [x0 - HX, x0 + OW + HX)
+            constexpr int HX = Halo<T, 4>::HX, OW = Halo<T, 4>::OW;
+            const int sx = j % I.nsx, sy = j / I.nsx;
+            const int nsy = (I.ny + I.rows - 1) / I.rows;
+            const int y0 = sy * I.rows, y1 = min(y0 + I.rows, I.ny);
+            const int ylo = max(y0 - T, 0), yhi = min(y1 + T, I.ny) - 1;
+            const int xlo = max(sx * OW - HX, 0), xhi = sx * OW + OW + HX - 1;
+            const int sy_lo = ylo / I.rows, sy_hi = min(yhi / I.rows, nsy - 1);
+            const int sx_lo = xlo / OW, sx_hi = min(xhi / OW, I.nsx - 1);
             long long polls = 0;
-            while (__hip_atomic_load(&a.done[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
-                   target) {
-                if (++polls > a.spin_limit) {
-                    __hip_atomic_store(a.abort_flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    return;
+            for (int qy = sy_lo; qy <= sy_hi; ++qy)
+                for (int qx = sx_lo; qx <= sx_hi; ++qx) {
+                    const unsigned *f = &a.flags[I.strip0 + qy * I.nsx + qx];
+                    while (__hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
+                           (unsigned)tau) {
+                        if (++polls > a.spin_limit) {
+                            __hip_atomic_store(a.abort_flag, 1u, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+                            return;
+                        }
+                        __builtin_amdgcn_s_sleep(2);
+                    }
                 }
-                __builtin_amdgcn_s_sleep(8);
-            }
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         }
 
@@ -127,20 +146,34 @@ __global__ __launch_bounds__(256) void batch_kernel(BatchArgs a)
 
         if (diag) {
             const double sb = wave_sum64(acc.sb), sn = wave_sum64(acc.sn), m2 = wave_max64(acc.m2);
+            const int s = (tau + 1) / a.seb - 1; // sample index within this run
+            if (PERSIST && s > 0) {
+                // the partial slot of this strip still holds sample s-1 until it is reduced
+                long long polls = 0;
+                while (__hip_atomic_load(&a.fin[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
+                       (unsigned)s) {
+                    if (++polls > a.spin_limit) {
+                        __hip_atomic_store(a.abort_flag, 1u, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                        return;
+                    }
+                    __builtin_amdgcn_s_sleep(2);
+                }
+            }
             if (lane == 0) {
                 a.partials[3 * (size_t)local + 0] = sb;
                 a.partials[3 * (size_t)local + 1] = sn;
                 a.partials[3 * (size_t)local + 2] = m2;
             }
-            __threadfence();
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
             unsigned prev = 0;
             if (lane == 0)
-                prev = __hip_atomic_fetch_add(&a.arrive[k], 1u, __ATOMIC_ACQ_REL,
+                prev = __hip_atomic_fetch_add(&a.arrive[k], 1u, __ATOMIC_RELAXED,
                                               __HIP_MEMORY_SCOPE_AGENT);
             prev = __builtin_amdgcn_readfirstlane(prev);
-            const int s = (tau + 1) / a.seb - 1; // sample index within this run
             if (prev + 1 == (unsigned)(s + 1) * (unsigned)I.nstrips) {
-                __threadfence();
+                // last strip of this sample: fold the partials in strip order
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
                 double tb = 0.0, tn = 0.0, tm = -1.0;
                 for (int jj = lane; jj < I.nstrips; jj += 64) {
                     const size_t q = 3 * (size_t)(I.strip0 + jj);
@@ -161,25 +194,34 @@ __global__ __launch_bounds__(256) void batch_kernel(BatchArgs a)
                     o[2] = I.h * I.h * tn;
                     o[3] = tm < 0.0 ? 0.0 : I.h * sqrt(tm);
                 }
+                if (PERSIST) {
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+                    if (lane == 0)
+                        __hip_atomic_store(&a.fin[k], (unsigned)(s + 1), __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                }
             }
         }
         if (PERSIST) {
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); // this strip's stores first
             if (lane == 0)
-                __hip_atomic_fetch_add(&a.done[k], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&a.flags[local], (unsigned)(tau + 1), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
         } else {
             return;
         }
     }
 }
 
-__global__ void batch_zero(unsigned *done, unsigned *arrive, int count, unsigned *abort_flag,
-                           unsigned long long *next)
+__global__ void batch_zero(unsigned *flags, int S, unsigned *arrive, unsigned *fin, int count,
+                           unsigned *abort_flag, unsigned long long *next)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < S)
+        flags[i] = 0u;
     if (i < count) {
-        done[i] = 0u;
         arrive[i] = 0u;
+        fin[i] = 0u;
     }
     if (i == 0) {
         *abort_flag = 0u;
@@ -246,9 +288,10 @@ struct kb_batch {
     char *arena = nullptr;
     BInst *dinst = nullptr;
     int *dstrip_inst = nullptr;
+    unsigned *dflags = nullptr;
     double *dpartials = nullptr, *dseries = nullptr, *dwin = nullptr, *dv = nullptr;
     int *dnpts = nullptr;
-    unsigned *dcnt = nullptr; // done[count], arrive[count], abort
+    unsigned *dcnt = nullptr; // arrive[count], fin[count], abort
     unsigned long long *dnext = nullptr;
     double *dcheck = nullptr; // input-check partials
     double *hpin = nullptr;   // pinned staging
@@ -335,8 +378,12 @@ int layout(kb_batch *b, int T)
         (void)hipFree(b->dstrip_inst);
     if (b->dpartials)
         (void)hipFree(b->dpartials);
+    if (b->dflags)
+        (void)hipFree(b->dflags);
     b->dstrip_inst = nullptr;
     b->dpartials = nullptr;
+    b->dflags = nullptr;
+    KB_HIP(b, hipMalloc((void **)&b->dflags, (size_t)S * sizeof(unsigned)));
     KB_HIP(b, hipMalloc((void **)&b->dstrip_inst, (size_t)S * sizeof(int)));
     KB_HIP(b, hipMalloc((void **)&b->dpartials, (size_t)S * 3 * sizeof(double)));
     KB_HIP(b, hipMemcpyAsync(b->dstrip_inst, si.data(), (size_t)S * sizeof(int),
@@ -423,7 +470,7 @@ void kb_destroy(kb_batch *b)
     if (!b)
         return;
     (void)hipStreamSynchronize(b->stream);
-    void *ptrs[] = {b->arena, b->dinst, b->dstrip_inst, b->dpartials, b->dseries, b->dwin,
+    void *ptrs[] = {b->arena, b->dinst, b->dstrip_inst, b->dflags, b->dpartials, b->dseries, b->dwin,
                     b->dv, b->dnpts, b->dcnt, b->dnext, b->dcheck};
     for (void *p : ptrs)
         if (p)
@@ -631,16 +678,20 @@ int kb_run(kb_batch *b, int64_t nsteps, int32_t sample_every)
     a.sample_base = b->nsamp;
     a.cap = b->cap;
     a.step_base = b->steps;
-    a.done = b->dcnt;
-    a.arrive = b->dcnt + b->count;
+    a.flags = b->dflags;
+    a.arrive = b->dcnt;
+    a.fin = b->dcnt + b->count;
     a.abort_flag = b->dcnt + 2 * b->count;
     a.next = b->dnext;
     a.partials = b->dpartials;
     a.series = b->dseries;
     a.spin_limit = b->spin_limit;
 
-    hipLaunchKernelGGL(kc::batch_zero, dim3((b->count + 255) / 256), dim3(256), 0, b->stream,
-                       a.done, a.arrive, b->count, a.abort_flag, a.next);
+    {
+        const int nz = b->S > b->count ? b->S : b->count;
+        hipLaunchKernelGGL(kc::batch_zero, dim3((nz + 255) / 256), dim3(256), 0, b->stream,
+                           a.flags, b->S, a.arrive, a.fin, b->count, a.abort_flag, a.next);
+    }
     KB_HIP(b, hipGetLastError());
     if (b->persistent) {
         const void *fn = nullptr;
