@@ -70,13 +70,19 @@ template <int T, int LAW, int PF, bool PERSIST>
 __global__ __launch_bounds__(256) void batch_kernel(BatchArgs a)
 {
     const int lane = threadIdx.x & 63;
+    long long taken = 0; // items handled by this wavefront, at most all of them
     for (;;) {
+        if (PERSIST && ++taken > a.total_items) {
+            __hip_atomic_store(a.abort_flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return;
+        }
+        // The loop body has no lane-divergent branches: every lane performs the
+        // (identical) stores and the counters are bumped by lane 0's share only,
+        // so the wavefront stays converged around the wave-wide broadcasts.
         unsigned long long item;
         if (PERSIST) {
-            unsigned long long got = 0;
-            if (lane == 0)
-                got = __hip_atomic_fetch_add(a.next, 1ull, __ATOMIC_RELAXED,
-                                             __HIP_MEMORY_SCOPE_AGENT);
+            const unsigned long long got = __hip_atomic_fetch_add(
+                a.next, lane == 0 ? 1ull : 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             item = bcast64(got);
             if (item >= (unsigned long long)a.total_items)
                 return;
@@ -160,17 +166,12 @@ __global__ __launch_bounds__(256) void batch_kernel(BatchArgs a)
                     __builtin_amdgcn_s_sleep(2);
                 }
             }
-            if (lane == 0) {
-                a.partials[3 * (size_t)local + 0] = sb;
-                a.partials[3 * (size_t)local + 1] = sn;
-                a.partials[3 * (size_t)local + 2] = m2;
-            }
+            a.partials[3 * (size_t)local + 0] = sb;
+            a.partials[3 * (size_t)local + 1] = sn;
+            a.partials[3 * (size_t)local + 2] = m2;
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-            unsigned prev = 0;
-            if (lane == 0)
-                prev = __hip_atomic_fetch_add(&a.arrive[k], 1u, __ATOMIC_RELAXED,
-                                              __HIP_MEMORY_SCOPE_AGENT);
-            prev = __builtin_amdgcn_readfirstlane(prev);
+            const unsigned prev = __builtin_amdgcn_readfirstlane(__hip_atomic_fetch_add(
+                &a.arrive[k], lane == 0 ? 1u : 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
             if (prev + 1 == (unsigned)(s + 1) * (unsigned)I.nstrips) {
                 // last strip of this sample: fold the partials in strip order
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
@@ -187,26 +188,22 @@ __global__ __launch_bounds__(256) void batch_kernel(BatchArgs a)
                 tb = wave_sum64(tb);
                 tn = wave_sum64(tn);
                 tm = wave_max64(tm);
-                if (lane == 0) {
-                    double *o = a.series + ((size_t)k * a.cap + a.sample_base + s) * 4;
-                    o[0] = (double)(a.step_base + (long long)(tau + 1) * a.T) * I.dt;
-                    o[1] = I.h * I.h * tb;
-                    o[2] = I.h * I.h * tn;
-                    o[3] = tm < 0.0 ? 0.0 : I.h * sqrt(tm);
-                }
+                double *o = a.series + ((size_t)k * a.cap + a.sample_base + s) * 4;
+                o[0] = (double)(a.step_base + (long long)(tau + 1) * a.T) * I.dt;
+                o[1] = I.h * I.h * tb;
+                o[2] = I.h * I.h * tn;
+                o[3] = tm < 0.0 ? 0.0 : I.h * sqrt(tm);
                 if (PERSIST) {
                     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-                    if (lane == 0)
-                        __hip_atomic_store(&a.fin[k], (unsigned)(s + 1), __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_AGENT);
+                    __hip_atomic_store(&a.fin[k], (unsigned)(s + 1), __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
                 }
             }
         }
         if (PERSIST) {
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); // this strip's stores first
-            if (lane == 0)
-                __hip_atomic_store(&a.flags[local], (unsigned)(tau + 1), __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&a.flags[local], (unsigned)(tau + 1), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
         } else {
             return;
         }
