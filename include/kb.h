@@ -85,7 +85,9 @@ int kb_fit_velocity(kb_batch *bt, const double *r_lo, const double *r_hi, double
  * divides sample_every is used); rows: output rows per strip for each
  * instance (count entries, or NULL to keep); prefetch 2 or 4 (0 keeps);
  * persistent: 1 = one launch per kb_run, 0 = one launch per time block,
- * -1 keeps.  Results are bitwise independent of all of these. */
+ * -1 keeps.  Fields, sample times and radii are bitwise independent of all
+ * of these; the double-precision mass and nutrient sums are folded per strip,
+ * so a different strip partition changes them at the level of rounding. */
 int kb_set_tuning(kb_batch *bt, int32_t tsteps, const int32_t *rows, int32_t prefetch,
                   int32_t persistent);
 int kb_get_tuning(const kb_batch *bt, int32_t *tsteps, int32_t *rows, int32_t *prefetch,

@@ -87,7 +87,10 @@ def test_persistent_equals_per_block_launches_and_any_tuning():
         if ref is None:
             ref = got
             continue
-        assert np.array_equal(got[0], ref[0]), tune
+        # fields, times and radii are exact; the double sums are folded per strip,
+        # so another strip partition changes their rounding only
+        assert np.array_equal(got[0][..., [0, 3]], ref[0][..., [0, 3]]), tune
+        np.testing.assert_allclose(got[0][..., 1:3], ref[0][..., 1:3], rtol=1e-13, atol=0)
         for (a, b_), (c, d) in zip(got[1], ref[1]):
             assert np.array_equal(a, c) and np.array_equal(b_, d), tune
 
@@ -166,7 +169,9 @@ def test_batch_autotune_keeps_results():
     T, rows, pf, _p = B.tuning()
     assert every % T == 0 and np.all(rows >= 1) and pf in (2, 4)
     B.run(steps, every)
-    assert np.array_equal(B.series(), ref[0])
+    ser = B.series()
+    assert np.array_equal(ser[..., [0, 3]], ref[0][..., [0, 3]])
+    np.testing.assert_allclose(ser[..., 1:3], ref[0][..., 1:3], rtol=1e-13, atol=0)
     for k in range(len(INSTANCES)):
         gb, gn = B.get_fields(k)
         assert np.array_equal(gb, ref[1][k][0]) and np.array_equal(gn, ref[1][k][1])
