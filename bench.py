@@ -96,7 +96,7 @@ def run(args):
     tsteps, rows, pf = S.tuning()
 
     nsamp = args.steps // SAMPLE_EVERY + 2
-    series = torch.zeros((nsamp, 4), dtype=torch.float64, device=dev)
+    series = torch.zeros((nsamp, 5), dtype=torch.float64, device=dev)
 
     # warmup (same code path)
     left = args.warmup
@@ -161,7 +161,7 @@ def run(args):
         "effective_hbm_frac": round(value * 1e9 * 20 / (HBM_PEAK_GBS * 1e9), 4),
         "wall_s": round(wall, 3),
         "final_diag": {"t": float(last[0]), "mass": float(last[1]), "nutrient": float(last[2]),
-                       "envelope_radius": float(last[3])},
+                       "envelope_radius": float(last[3]), "area_radius": float(last[4])},
     }
     S.close()
     if not args.no_cpu_baseline:

@@ -60,13 +60,13 @@ int kb_set_fields(kb_batch *bt, int32_t k, const float *b0, const float *n0, con
                   int mem);
 
 /* Advance every instance by nsteps (a multiple of sample_every >= 1) and
- * record {t, mass, nutrient, envelope_radius} of every instance after each
- * sample_every steps.  One persistent launch (or, with persistent = 0 in
+ * record {t, mass, nutrient, envelope_radius, area_radius} (as
+ * kc_diagnostics_device) of every instance after each sample_every steps.  One persistent launch (or, with persistent = 0 in
  * kb_set_tuning, one launch per time block).  Enqueued; fails with
  * KC_EINVAL when the samples would exceed max_samples. */
 int kb_run(kb_batch *bt, int64_t nsteps, int32_t sample_every);
 
-/* Copy the samples out: out is [count][max_samples][4] doubles (unused
+/* Copy the samples out: out is [count][max_samples][5] doubles (unused
  * entries are zero); *nsamples (may be NULL) receives the number recorded.
  * Synchronous. */
 int kb_series(kb_batch *bt, double *out, int32_t *nsamples, int mem);
@@ -74,12 +74,15 @@ int kb_series(kb_batch *bt, double *out, int32_t *nsamples, int mem);
 /* Current fields of instance k (synchronous). */
 int kb_get_fields(kb_batch *bt, int32_t k, float *b, float *n, int mem);
 
-/* Least-squares slope dR/dt of each instance's recorded envelope radius over
- * the samples with r_lo[k] <= R <= r_hi[k] (host arrays of count doubles).
- * v[k] is NaN when fewer than 3 samples qualify; npoints (may be NULL)
- * receives the sample counts.  Computed on the device; synchronous. */
-int kb_fit_velocity(kb_batch *bt, const double *r_lo, const double *r_hi, double *v,
-                    int32_t *npoints);
+enum { KB_RADIUS_ENVELOPE = 0, KB_RADIUS_AREA = 1 };
+
+/* Least-squares slope dR/dt of each instance's recorded radius (envelope or
+ * area, `radius`) over the samples with r_lo[k] <= R <= r_hi[k] (host arrays
+ * of count doubles).  v[k] is NaN when fewer than 3 samples qualify; npoints
+ * (may be NULL) receives the sample counts.  Computed on the device;
+ * synchronous. */
+int kb_fit_velocity(kb_batch *bt, int32_t radius, const double *r_lo, const double *r_hi,
+                    double *v, int32_t *npoints);
 
 /* Kernel configuration.  tsteps: steps per time block (a compiled depth that
  * divides sample_every is used); rows: output rows per strip for each

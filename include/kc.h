@@ -105,9 +105,11 @@ int kc_step(kc_ctx *ctx, int64_t nsteps);
  *   (0 when no cell qualifies).  Any output pointer may be NULL. */
 int kc_diagnostics(kc_ctx *ctx, double *mass, double *nutrient, double *envelope_radius);
 
-/* Same diagnostics, enqueued: writes {time, mass, nutrient, envelope_radius}
- * as 4 doubles to device memory dev_out4 when the stream reaches it. */
-int kc_diagnostics_device(kc_ctx *ctx, double *dev_out4);
+/* Same diagnostics, enqueued: writes 5 doubles {time, mass, nutrient,
+ * envelope_radius, area_radius} to device memory dev_out5 when the stream
+ * reaches it; area_radius = h sqrt(N / pi), N the number of cells with
+ * b >= b_thr (the radius of a disc of the colony's area). */
+int kc_diagnostics_device(kc_ctx *ctx, double *dev_out5);
 
 /* Copy the current level out (synchronous).  Either pointer may be NULL. */
 int kc_get_fields(kc_ctx *ctx, void *b, void *n, int mem);

@@ -57,7 +57,7 @@ def _load():
         lib.oracle_run.restype = ctypes.c_int
         lib.oracle_diag.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, dp, dp,
                                     ctypes.c_double, ctypes.c_double, ctypes.c_double,
-                                    dp, dp, dp]
+                                    dp, dp, dp, dp]
         lib.oracle_diag.restype = None
         lib.oracle_threads.argtypes = []
         lib.oracle_threads.restype = ctypes.c_int
@@ -101,16 +101,19 @@ def run(b, n, sigma, h, dt, nsteps, **p):
     return b, n
 
 
-def diag(b, n, h, b_thr, cx=None, cy=None):
-    """(mass, nutrient, envelope radius) of one level; centre defaults to the grid centre."""
+def diag(b, n, h, b_thr, cx=None, cy=None, area=False):
+    """(mass, nutrient, envelope radius) of one level -- plus the area radius
+    when area=True; the centre defaults to the grid centre."""
     lib = _load()
     b, n = _f64(b), _f64(n)
     ny, nx = b.shape
     cx = (nx - 1) / 2.0 if cx is None else float(cx)
     cy = (ny - 1) / 2.0 if cy is None else float(cy)
-    m, nu, r = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    m, nu, r, ra = ctypes.c_double(), ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
     lib.oracle_diag(nx, ny, float(h), _ptr(b), _ptr(n), float(b_thr), cx, cy,
-                    ctypes.byref(m), ctypes.byref(nu), ctypes.byref(r))
+                    ctypes.byref(m), ctypes.byref(nu), ctypes.byref(r), ctypes.byref(ra))
+    if area:
+        return m.value, nu.value, r.value, ra.value
     return m.value, nu.value, r.value
 
 

@@ -139,20 +139,23 @@ int oracle_run(int nx, int ny, double h, double dt,
  *   nutrient = h^2 * sum n
  *   radius   = h * max over cells with b >= b_thr of the distance of the
  *              cell index (i, j) from (cx, cy); 0 when no cell qualifies.
- * The paper tracks the front of b near a fixed level (Sec. 4.2); the
- * two-dimensional envelope radius used here is that idea on the grid.
+ *   area_radius = h * sqrt(count of cells with b >= b_thr / pi): the radius
+ *              of the disc with the colony's area.
+ * The paper tracks the front of b near a fixed level (Sec. 4.2); both radii
+ * carry that idea to a two-dimensional colony.
  */
 void oracle_diag(int nx, int ny, double h, const double *b, const double *n,
                  double b_thr, double cx, double cy,
-                 double *mass, double *nutrient, double *radius)
+                 double *mass, double *nutrient, double *radius, double *area_radius)
 {
-    double sb = 0.0, sn = 0.0, rmax = 0.0;
+    double sb = 0.0, sn = 0.0, rmax = 0.0, count = 0.0;
     for (int j = 0; j < ny; ++j) {
         for (int i = 0; i < nx; ++i) {
             const long p = (long)j * nx + i;
             sb += b[p];
             sn += n[p];
             if (b[p] >= b_thr) {
+                count += 1.0;
                 const double dx = (double)i - cx, dy = (double)j - cy;
                 const double d = sqrt(dx * dx + dy * dy);
                 if (d > rmax)
@@ -163,6 +166,7 @@ void oracle_diag(int nx, int ny, double h, const double *b, const double *n,
     *mass = h * h * sb;
     *nutrient = h * h * sn;
     *radius = h * rmax;
+    *area_radius = h * sqrt(count / 3.14159265358979323846);
 }
 
 /* Number of OpenMP threads oracle_step runs with (1 without OpenMP). */

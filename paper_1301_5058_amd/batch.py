@@ -76,8 +76,8 @@ class Batch:
         return ns.value
 
     def series(self):
-        """[count, nsamples, 4] array of (t, mass, nutrient, envelope radius)."""
-        out = np.zeros((self.count, self.max_samples, 4), dtype=np.float64)
+        """[count, nsamples, 5] array of (t, mass, nutrient, envelope radius, area radius)."""
+        out = np.zeros((self.count, self.max_samples, 5), dtype=np.float64)
         ns = ctypes.c_int32()
         self._chk(N.lib().kb_series(self.h, ctypes.c_void_p(out.ctypes.data), ctypes.byref(ns),
                                     N.KC_MEM_HOST))
@@ -90,12 +90,13 @@ class Batch:
                                         ctypes.c_void_p(n.ctypes.data), N.KC_MEM_HOST))
         return b, n
 
-    def fit_velocity(self, r_lo, r_hi):
+    def fit_velocity(self, r_lo, r_hi, radius="envelope"):
         lo = np.ascontiguousarray(np.broadcast_to(np.asarray(r_lo, np.float64), (self.count,)))
         hi = np.ascontiguousarray(np.broadcast_to(np.asarray(r_hi, np.float64), (self.count,)))
         v = np.empty(self.count, dtype=np.float64)
         npts = np.empty(self.count, dtype=np.int32)
-        self._chk(N.lib().kb_fit_velocity(self.h, ctypes.c_void_p(lo.ctypes.data),
+        sel = 0 if radius == "envelope" else 1
+        self._chk(N.lib().kb_fit_velocity(self.h, sel, ctypes.c_void_p(lo.ctypes.data),
                                           ctypes.c_void_p(hi.ctypes.data),
                                           ctypes.c_void_p(v.ctypes.data),
                                           ctypes.c_void_p(npts.ctypes.data)))

@@ -14,7 +14,8 @@
 //   PERSIST = false: one launch per time block, item = wavefront index.
 // On a sampling block each strip also folds the cells it stores into double
 // partials; the last strip of the instance to arrive (arrive[k] counter) sums
-// the partials in strip order and writes {t, mass, nutrient, radius}.
+// the partials in strip order and writes {t, mass, nutrient, envelope radius,
+// area radius}.
 // kb_fit: least-squares slope of each instance's R(t) over a radius window.
 #include <math.h>
 #include <stdarg.h>
@@ -54,8 +55,8 @@ struct BatchArgs {
     unsigned *flags;  // [S] progress of every strip: blocks completed
     unsigned *fin;    // [count] samples of this run already reduced
     unsigned *arrive, *abort_flag;
-    double *partials; // [S][3]
-    double *series;   // [count][cap][4]
+    double *partials; // [S][4]
+    double *series;   // [count][cap][5]
     long long spin_limit;
 };
 
@@ -144,7 +145,7 @@ __global__ __launch_bounds__(256) void batch_kernel(BatchArgs a)
         sa.cx = I.cx;
         sa.cy = I.cy;
         const bool diag = ((tau + 1) % a.seb) == 0;
-        DiagAcc acc{0.0, 0.0, -1.0};
+        DiagAcc acc{0.0, 0.0, -1.0, 0.0};
         if (diag)
             stream_strip<float, T, LAW, PF, true>(sa, j % I.nsx, j / I.nsx, acc);
         else
@@ -152,6 +153,7 @@ __global__ __launch_bounds__(256) void batch_kernel(BatchArgs a)
 
         if (diag) {
             const double sb = wave_sum64(acc.sb), sn = wave_sum64(acc.sn), m2 = wave_max64(acc.m2);
+            const double ct = wave_sum64(acc.cnt);
             const int s = (tau + 1) / a.seb - 1; // sample index within this run
             if (PERSIST && s > 0) {
                 // the partial slot of this strip still holds sample s-1 until it is reduced
@@ -166,33 +168,38 @@ __global__ __launch_bounds__(256) void batch_kernel(BatchArgs a)
                     __builtin_amdgcn_s_sleep(2);
                 }
             }
-            a.partials[3 * (size_t)local + 0] = sb;
-            a.partials[3 * (size_t)local + 1] = sn;
-            a.partials[3 * (size_t)local + 2] = m2;
+            a.partials[4 * (size_t)local + 0] = sb;
+            a.partials[4 * (size_t)local + 1] = sn;
+            a.partials[4 * (size_t)local + 2] = m2;
+            a.partials[4 * (size_t)local + 3] = ct;
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
             const unsigned prev = __builtin_amdgcn_readfirstlane(__hip_atomic_fetch_add(
                 &a.arrive[k], lane == 0 ? 1u : 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
             if (prev + 1 == (unsigned)(s + 1) * (unsigned)I.nstrips) {
                 // last strip of this sample: fold the partials in strip order
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-                double tb = 0.0, tn = 0.0, tm = -1.0;
+                double tb = 0.0, tn = 0.0, tm = -1.0, tc = 0.0;
                 for (int jj = lane; jj < I.nstrips; jj += 64) {
-                    const size_t q = 3 * (size_t)(I.strip0 + jj);
+                    const size_t q = 4 * (size_t)(I.strip0 + jj);
                     tb += __hip_atomic_load(&a.partials[q + 0], __ATOMIC_RELAXED,
                                             __HIP_MEMORY_SCOPE_AGENT);
                     tn += __hip_atomic_load(&a.partials[q + 1], __ATOMIC_RELAXED,
                                             __HIP_MEMORY_SCOPE_AGENT);
                     tm = fmax(tm, __hip_atomic_load(&a.partials[q + 2], __ATOMIC_RELAXED,
                                                     __HIP_MEMORY_SCOPE_AGENT));
+                    tc += __hip_atomic_load(&a.partials[q + 3], __ATOMIC_RELAXED,
+                                            __HIP_MEMORY_SCOPE_AGENT);
                 }
                 tb = wave_sum64(tb);
                 tn = wave_sum64(tn);
                 tm = wave_max64(tm);
-                double *o = a.series + ((size_t)k * a.cap + a.sample_base + s) * 4;
+                tc = wave_sum64(tc);
+                double *o = a.series + ((size_t)k * a.cap + a.sample_base + s) * 5;
                 o[0] = (double)(a.step_base + (long long)(tau + 1) * a.T) * I.dt;
                 o[1] = I.h * I.h * tb;
                 o[2] = I.h * I.h * tn;
                 o[3] = tm < 0.0 ? 0.0 : I.h * sqrt(tm);
+                o[4] = I.h * sqrt(tc / 3.14159265358979323846);
                 if (PERSIST) {
                     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
                     __hip_atomic_store(&a.fin[k], (unsigned)(s + 1), __ATOMIC_RELAXED,
@@ -233,20 +240,21 @@ __global__ void series_zero(double *series, size_t n)
         series[i] = 0.0;
 }
 
-// Least-squares slope per instance, one wavefront each, fixed order.
-__global__ __launch_bounds__(64) void kb_fit(const double *series, int cap, int nsamp,
+// Least-squares slope per instance, one wavefront each, fixed order; `col`
+// selects the radius (3 envelope, 4 area) of the 5-double samples.
+__global__ __launch_bounds__(64) void kb_fit(const double *series, int cap, int nsamp, int col,
                                              const double *win, double *v, int *npts)
 {
     const int k = blockIdx.x;
     const int lane = threadIdx.x;
     const double lo = win[2 * k], hi = win[2 * k + 1];
-    const double *S = series + (size_t)k * cap * 4;
+    const double *S = series + (size_t)k * cap * 5;
     double c = 0.0, st = 0.0, sr = 0.0;
     for (int s = lane; s < nsamp; s += 64) {
-        const double R = S[4 * s + 3];
+        const double R = S[5 * s + col];
         if (R >= lo && R <= hi) {
             c += 1.0;
-            st += S[4 * s + 0];
+            st += S[5 * s + 0];
             sr += R;
         }
     }
@@ -256,9 +264,9 @@ __global__ __launch_bounds__(64) void kb_fit(const double *series, int cap, int 
     const double tm = c > 0 ? st / c : 0.0, rm = c > 0 ? sr / c : 0.0;
     double sxy = 0.0, sxx = 0.0;
     for (int s = lane; s < nsamp; s += 64) {
-        const double R = S[4 * s + 3];
+        const double R = S[5 * s + col];
         if (R >= lo && R <= hi) {
-            const double dt = S[4 * s + 0] - tm;
+            const double dt = S[5 * s + 0] - tm;
             sxy += dt * (R - rm);
             sxx += dt * dt;
         }
@@ -382,7 +390,7 @@ int layout(kb_batch *b, int T)
     b->dflags = nullptr;
     KB_HIP(b, hipMalloc((void **)&b->dflags, (size_t)S * sizeof(unsigned)));
     KB_HIP(b, hipMalloc((void **)&b->dstrip_inst, (size_t)S * sizeof(int)));
-    KB_HIP(b, hipMalloc((void **)&b->dpartials, (size_t)S * 3 * sizeof(double)));
+    KB_HIP(b, hipMalloc((void **)&b->dpartials, (size_t)S * 4 * sizeof(double)));
     KB_HIP(b, hipMemcpyAsync(b->dstrip_inst, si.data(), (size_t)S * sizeof(int),
                              hipMemcpyHostToDevice, b->stream));
     KB_HIP(b, hipMemcpyAsync(b->dinst, b->hinst.data(), b->count * sizeof(BInst),
@@ -520,7 +528,7 @@ int kb_create(int32_t count, const kb_instance *inst, int32_t chi_law, int32_t m
     if (e == hipSuccess)
         e = hipMalloc((void **)&b->dinst, count * sizeof(BInst));
     if (e == hipSuccess)
-        e = hipMalloc((void **)&b->dseries, (size_t)count * max_samples * 4 * sizeof(double));
+        e = hipMalloc((void **)&b->dseries, (size_t)count * max_samples * 5 * sizeof(double));
     if (e == hipSuccess)
         e = hipMalloc((void **)&b->dwin, (size_t)count * 2 * sizeof(double));
     if (e == hipSuccess)
@@ -563,7 +571,7 @@ int kb_create(int32_t count, const kb_instance *inst, int32_t chi_law, int32_t m
             b->rows[k] = default_rows_for(I.nx, I.ny);
         }
         hipLaunchKernelGGL(kc::series_zero, dim3(256), dim3(256), 0, b->stream, b->dseries,
-                           (size_t)count * max_samples * 4);
+                           (size_t)count * max_samples * 5);
         if (hipGetLastError() != hipSuccess)
             rc = KC_EHIP;
     }
@@ -631,7 +639,7 @@ int kb_set_fields(kb_batch *b, int32_t k, const float *b0, const float *n0, cons
     b->nsamp = 0;
     b->steps = 0;
     hipLaunchKernelGGL(kc::series_zero, dim3(256), dim3(256), 0, b->stream, b->dseries,
-                       (size_t)b->count * b->cap * 4);
+                       (size_t)b->count * b->cap * 5);
     KB_HIP(b, hipGetLastError());
     return KC_OK;
 }
@@ -734,7 +742,7 @@ int kb_series(kb_batch *b, double *out, int32_t *nsamples, int mem)
     if (nsamples)
         *nsamples = b->nsamp;
     if (out) {
-        KB_HIP(b, hipMemcpyAsync(out, b->dseries, (size_t)b->count * b->cap * 4 * sizeof(double),
+        KB_HIP(b, hipMemcpyAsync(out, b->dseries, (size_t)b->count * b->cap * 5 * sizeof(double),
                                  mem == KC_MEM_HOST ? hipMemcpyDeviceToHost
                                                     : hipMemcpyDeviceToDevice,
                                  b->stream));
@@ -763,14 +771,16 @@ int kb_get_fields(kb_batch *b, int32_t k, float *bo, float *no, int mem)
     return KC_OK;
 }
 
-int kb_fit_velocity(kb_batch *b, const double *r_lo, const double *r_hi, double *v,
-                    int32_t *npoints)
+int kb_fit_velocity(kb_batch *b, int32_t radius, const double *r_lo, const double *r_hi,
+                    double *v, int32_t *npoints)
 {
     if (!b)
         return KC_EINVAL;
     b->err.clear();
     if (!r_lo || !r_hi || !v)
         return bfail(b, KC_EINVAL, "null pointer");
+    if (radius != KB_RADIUS_ENVELOPE && radius != KB_RADIUS_AREA)
+        return bfail(b, KC_EINVAL, "bad radius selector %d", radius);
     if (ensure_pinned(b, 3 * (size_t)b->count) != KC_OK)
         return KC_ENOMEM;
     for (int k = 0; k < b->count; ++k) {
@@ -780,7 +790,7 @@ int kb_fit_velocity(kb_batch *b, const double *r_lo, const double *r_hi, double 
     KB_HIP(b, hipMemcpyAsync(b->dwin, b->hpin, 2 * b->count * sizeof(double),
                              hipMemcpyHostToDevice, b->stream));
     hipLaunchKernelGGL(kc::kb_fit, dim3(b->count), dim3(64), 0, b->stream, b->dseries, b->cap,
-                       b->nsamp, b->dwin, b->dv, b->dnpts);
+                       b->nsamp, radius == KB_RADIUS_AREA ? 4 : 3, b->dwin, b->dv, b->dnpts);
     KB_HIP(b, hipGetLastError());
     KB_HIP(b, hipMemcpyAsync(v, b->dv, b->count * sizeof(double), hipMemcpyDeviceToHost,
                              b->stream));

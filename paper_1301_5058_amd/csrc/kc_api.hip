@@ -32,9 +32,9 @@ struct kc_ctx {
     int64_t steps = 0;
     kc::Tuning tune{2, 32, 4};
     bool ref = false;
-    double *dparts = nullptr; // diagnostics partials, then out4 (4 doubles)
-    double *dout4 = nullptr;
-    double *hout = nullptr; // pinned host copy of out4
+    double *dparts = nullptr; // diagnostics partials, then out5 (5 doubles)
+    double *dout5 = nullptr;
+    double *hout = nullptr; // pinned host staging (input check partials, out5)
     std::string err;
 };
 
@@ -310,16 +310,16 @@ int kc_create(const kc_grid *g, double h, double dt, const kc_params *p, void *h
         const int np = kc::diag_parts(c->ny);
         const size_t cells = (size_t)c->nx * c->ny;
         const int cp = kc::check_parts(cells);
-        const size_t nparts = (size_t)(3 * np > 2 * cp ? 3 * np : 2 * cp);
-        e = hipMalloc((void **)&c->dparts, (nparts + 4) * sizeof(double));
+        const size_t nparts = (size_t)(4 * np > 2 * cp ? 4 * np : 2 * cp);
+        e = hipMalloc((void **)&c->dparts, (nparts + 5) * sizeof(double));
         if (e != hipSuccess)
             rc = e == hipErrorOutOfMemory ? KC_ENOMEM : KC_EHIP;
         else
-            c->dout4 = c->dparts + nparts;
+            c->dout5 = c->dparts + nparts;
     }
     if (rc == KC_OK) {
-        e = hipHostMalloc((void **)&c->hout, 2 * kc::check_parts((size_t)c->nx * c->ny) *
-                                                 sizeof(double) + 4 * sizeof(double),
+        e = hipHostMalloc((void **)&c->hout, (2 * kc::check_parts((size_t)c->nx * c->ny) + 5) *
+                                                 sizeof(double),
                           hipHostMallocDefault);
         if (e != hipSuccess)
             rc = KC_ENOMEM;
@@ -416,9 +416,9 @@ int kc_step(kc_ctx *c, int64_t nsteps)
     return c->p.precision == KC_FP32 ? step_impl<float>(c, nsteps) : step_impl<double>(c, nsteps);
 }
 
-int kc_diagnostics_device(kc_ctx *c, double *dev_out4)
+int kc_diagnostics_device(kc_ctx *c, double *dev_out5)
 {
-    if (!c || !dev_out4)
+    if (!c || !dev_out5)
         return KC_EINVAL;
     c->err.clear();
     if (!c->has_fields)
@@ -428,11 +428,11 @@ int kc_diagnostics_device(kc_ctx *c, double *dev_out4)
     if (c->p.precision == KC_FP32)
         e = kc::launch_diag<float>((const float *)c->b[c->cur], (const float *)c->n[c->cur], c->nx,
                                    c->ny, c->pitch, c->h, t, c->p.b_thr, c->p.cx, c->p.cy,
-                                   c->dparts, dev_out4, c->stream);
+                                   c->dparts, dev_out5, c->stream);
     else
         e = kc::launch_diag<double>((const double *)c->b[c->cur], (const double *)c->n[c->cur],
                                     c->nx, c->ny, c->pitch, c->h, t, c->p.b_thr, c->p.cx, c->p.cy,
-                                    c->dparts, dev_out4, c->stream);
+                                    c->dparts, dev_out5, c->stream);
     if (e != hipSuccess)
         return hipfail(c, e, "diagnostics launch");
     return KC_OK;
@@ -440,10 +440,10 @@ int kc_diagnostics_device(kc_ctx *c, double *dev_out4)
 
 int kc_diagnostics(kc_ctx *c, double *mass, double *nutrient, double *radius)
 {
-    const int rc = kc_diagnostics_device(c, c ? c->dout4 : nullptr);
+    const int rc = kc_diagnostics_device(c, c ? c->dout5 : nullptr);
     if (rc != KC_OK)
         return rc;
-    KC_HIP(c, hipMemcpyAsync(c->hout, c->dout4, 4 * sizeof(double), hipMemcpyDeviceToHost,
+    KC_HIP(c, hipMemcpyAsync(c->hout, c->dout5, 5 * sizeof(double), hipMemcpyDeviceToHost,
                              c->stream));
     KC_HIP(c, hipStreamSynchronize(c->stream));
     if (!isfinite(c->hout[1]) || !isfinite(c->hout[2]))

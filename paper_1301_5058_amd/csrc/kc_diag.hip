@@ -1,11 +1,12 @@
 // kc_diag.hip -- reductions over one field level, accumulated in double.
 //
-// diag_partial: block k reduces rows k, k + G, k + 2G, ...: sum b, sum n and
+// diag_partial: block k reduces rows k, k + G, k + 2G, ...: sum b, sum n,
 //   the largest squared distance from (cx, cy) of a cell with b >= b_thr
-//   (-1 when none).  Wavefront butterfly (xor shuffles) then a fixed LDS tree,
-//   so the result is the same bits on every run for a given grid.
+//   (-1 when none) and the number of such cells.  Wavefront butterfly (xor
+//   shuffles) then a fixed LDS tree, so the result is the same bits on every
+//   run for a given grid.
 // diag_final:   one block folds the partials in a fixed order and writes
-//   {t, h^2 sum b, h^2 sum n, h sqrt(max d^2)}.
+//   {t, h^2 sum b, h^2 sum n, h sqrt(max d^2), h sqrt(count / pi)}.
 // check_partial: input validation of dense device arrays: per block, the
 //   count of NaN / Inf / negative entries and the max of sigma n b.
 #include "kc_internal.h"
@@ -30,24 +31,28 @@ __device__ __forceinline__ double wave_max(double v)
     return v;
 }
 
-// Reduce three per-thread values over a 256-thread block; thread 0 gets them.
-__device__ __forceinline__ void block_reduce3(double &s0, double &s1, double &m2)
+// Reduce per-thread values over a 256-thread block (sums s0, s1, s3 and the
+// maximum m2); thread 0 gets them.
+__device__ __forceinline__ void block_reduce4(double &s0, double &s1, double &m2, double &s3)
 {
-    __shared__ double sh[3][4];
+    __shared__ double sh[4][4];
     s0 = wave_sum(s0);
     s1 = wave_sum(s1);
     m2 = wave_max(m2);
+    s3 = wave_sum(s3);
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
     if (l == 0) {
         sh[0][w] = s0;
         sh[1][w] = s1;
         sh[2][w] = m2;
+        sh[3][w] = s3;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
         s0 = (sh[0][0] + sh[0][1]) + (sh[0][2] + sh[0][3]);
         s1 = (sh[1][0] + sh[1][1]) + (sh[1][2] + sh[1][3]);
         m2 = fmax(fmax(sh[2][0], sh[2][1]), fmax(sh[2][2], sh[2][3]));
+        s3 = (sh[3][0] + sh[3][1]) + (sh[3][2] + sh[3][3]);
     }
 }
 
@@ -56,7 +61,7 @@ __global__ __launch_bounds__(256) void diag_partial(const R *b, const R *n, int 
                                                      int pitch, double b_thr, double cx, double cy,
                                                      double *parts)
 {
-    double sb = 0.0, sn = 0.0, m2 = -1.0;
+    double sb = 0.0, sn = 0.0, m2 = -1.0, cnt = 0.0;
     for (int y = blockIdx.x; y < ny; y += gridDim.x) {
         const R *rb = b + (size_t)y * pitch;
         const R *rn = n + (size_t)y * pitch;
@@ -68,32 +73,36 @@ __global__ __launch_bounds__(256) void diag_partial(const R *b, const R *n, int 
             if (bv >= b_thr) {
                 const double dx = (double)x - cx;
                 m2 = fmax(m2, dx * dx + dy * dy);
+                cnt += 1.0;
             }
         }
     }
-    block_reduce3(sb, sn, m2);
+    block_reduce4(sb, sn, m2, cnt);
     if (threadIdx.x == 0) {
-        parts[3 * blockIdx.x + 0] = sb;
-        parts[3 * blockIdx.x + 1] = sn;
-        parts[3 * blockIdx.x + 2] = m2;
+        parts[4 * blockIdx.x + 0] = sb;
+        parts[4 * blockIdx.x + 1] = sn;
+        parts[4 * blockIdx.x + 2] = m2;
+        parts[4 * blockIdx.x + 3] = cnt;
     }
 }
 
 __global__ __launch_bounds__(256) void diag_final(const double *parts, int nparts, double h,
-                                                   double t, double *out4)
+                                                   double t, double *out5)
 {
-    double sb = 0.0, sn = 0.0, m2 = -1.0;
+    double sb = 0.0, sn = 0.0, m2 = -1.0, cnt = 0.0;
     for (int i = threadIdx.x; i < nparts; i += 256) {
-        sb += parts[3 * i + 0];
-        sn += parts[3 * i + 1];
-        m2 = fmax(m2, parts[3 * i + 2]);
+        sb += parts[4 * i + 0];
+        sn += parts[4 * i + 1];
+        m2 = fmax(m2, parts[4 * i + 2]);
+        cnt += parts[4 * i + 3];
     }
-    block_reduce3(sb, sn, m2);
+    block_reduce4(sb, sn, m2, cnt);
     if (threadIdx.x == 0) {
-        out4[0] = t;
-        out4[1] = h * h * sb;
-        out4[2] = h * h * sn;
-        out4[3] = m2 < 0.0 ? 0.0 : h * sqrt(m2);
+        out5[0] = t;
+        out5[1] = h * h * sb;
+        out5[2] = h * h * sn;
+        out5[3] = m2 < 0.0 ? 0.0 : h * sqrt(m2);
+        out5[4] = h * sqrt(cnt / 3.14159265358979323846);
     }
 }
 
@@ -101,7 +110,7 @@ int diag_parts(int ny) { return ny < kDiagBlocks ? ny : kDiagBlocks; }
 
 template <typename R>
 hipError_t launch_diag(const R *b, const R *n, int nx, int ny, int pitch, double h, double t,
-                       double b_thr, double cx, double cy, double *parts, double *out4,
+                       double b_thr, double cx, double cy, double *parts, double *out5,
                        hipStream_t s)
 {
     const int np = diag_parts(ny);
@@ -110,7 +119,7 @@ hipError_t launch_diag(const R *b, const R *n, int nx, int ny, int pitch, double
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return e;
-    hipLaunchKernelGGL(diag_final, dim3(1), dim3(256), 0, s, parts, np, h, t, out4);
+    hipLaunchKernelGGL(diag_final, dim3(1), dim3(256), 0, s, parts, np, h, t, out5);
     return hipGetLastError();
 }
 
@@ -123,7 +132,7 @@ template <typename R>
 __global__ __launch_bounds__(256) void check_partial(const R *b, const R *n, const R *sg,
                                                       size_t cells, double *parts)
 {
-    double nbad = 0.0, mx = 0.0, unused = 0.0;
+    double nbad = 0.0, mx = 0.0, unused = 0.0, unused2 = 0.0;
     const size_t stride = (size_t)gridDim.x * 256;
     for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < cells; i += stride) {
         const R bv = b[i], nv = n[i], sv = sg[i];
@@ -134,7 +143,7 @@ __global__ __launch_bounds__(256) void check_partial(const R *b, const R *n, con
         else
             mx = fmax(mx, (double)sv * (double)nv * (double)bv);
     }
-    block_reduce3(nbad, unused, mx);
+    block_reduce4(nbad, unused, mx, unused2);
     if (threadIdx.x == 0) {
         parts[2 * blockIdx.x + 0] = nbad;
         parts[2 * blockIdx.x + 1] = mx;

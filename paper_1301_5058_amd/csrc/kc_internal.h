@@ -60,12 +60,13 @@ bool cache_lookup(const char *key, Tuning *t);
 void cache_store(const char *key, const Tuning &t, double gcells);
 int device_key(char *buf, size_t n, int nx, int ny, int precision, int chi_law);
 
-// Diagnostics: partial sums over row blocks, then one fixed-order final pass
-// writing {t, mass, nutrient, radius} to out4 (device doubles).
+// Diagnostics: partial sums over row blocks (4 doubles each), then one
+// fixed-order final pass writing {t, mass, nutrient, envelope radius, area
+// radius} to out5 (device doubles).
 int diag_parts(int ny);
 template <typename R>
 hipError_t launch_diag(const R *b, const R *n, int nx, int ny, int pitch, double h, double t,
-                       double b_thr, double cx, double cy, double *parts, double *out4,
+                       double b_thr, double cx, double cy, double *parts, double *out5,
                        hipStream_t s);
 
 // Input check of dense device arrays: block k writes parts[2k] = number of

@@ -88,7 +88,7 @@ __global__ __launch_bounds__(256) void step_stream(StepArgs<R> a)
     sa.rows = a.rows;
     sa.c = a.c;
     sa.b_thr = sa.cx = sa.cy = 0.0;
-    DiagAcc acc{0.0, 0.0, -1.0};
+    DiagAcc acc{0.0, 0.0, -1.0, 0.0};
     stream_strip<R, T, LAW, PF, false>(sa, strip % a.nsx, strip / a.nsx, acc);
 }
 

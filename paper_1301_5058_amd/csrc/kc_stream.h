@@ -13,7 +13,8 @@
 //
 // With DIAG set, the cells a strip stores are also folded into a per-lane
 // accumulator (sum b, sum n in double, largest squared distance from the
-// envelope centre of a cell with b >= b_thr), in a fixed order.
+// envelope centre of a cell with b >= b_thr, count of such cells), in a fixed
+// order.
 #pragma once
 
 #include "kc_device.h"
@@ -44,7 +45,7 @@ template <typename R> struct StripArgs {
 };
 
 struct DiagAcc {
-    double sb, sn, m2;
+    double sb, sn, m2, cnt;
 };
 
 template <typename R, int T, int LAW, int PF, bool DIAG>
@@ -187,6 +188,7 @@ __device__ __forceinline__ void stream_strip(const StripArgs<R> &a, int sx, int 
                                 if (bv >= a.b_thr) {
                                     const double dx = (double)(x0 + k) - a.cx;
                                     acc.m2 = fmax(acc.m2, dx * dx + dy * dy);
+                                    acc.cnt += 1.0;
                                 }
                             }
                         }

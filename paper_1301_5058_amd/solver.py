@@ -89,12 +89,20 @@ class Solver:
                                        ctypes.byref(r)), self.ctx)
         return m.value, nu.value, r.value
 
-    def diagnostics_device(self, out4):
-        """Enqueue {t, mass, nutrient, radius} into a float64 CUDA tensor view of 4 elements."""
-        if out4.dtype != torch.float64 or not out4.is_cuda or out4.numel() < 4 or \
-                not out4.is_contiguous():
-            raise ValueError("out4 must be a contiguous float64 CUDA tensor with >= 4 elements")
-        N.check(N.lib().kc_diagnostics_device(self.ctx, ctypes.c_void_p(out4.data_ptr())), self.ctx)
+    def diagnostics_device(self, out5):
+        """Enqueue {t, mass, nutrient, envelope radius, area radius} into a
+        contiguous float64 CUDA tensor of >= 5 elements."""
+        if out5.dtype != torch.float64 or not out5.is_cuda or out5.numel() < 5 or \
+                not out5.is_contiguous():
+            raise ValueError("out5 must be a contiguous float64 CUDA tensor with >= 5 elements")
+        N.check(N.lib().kc_diagnostics_device(self.ctx, ctypes.c_void_p(out5.data_ptr())), self.ctx)
+
+    def diagnostics_all(self):
+        """(t, mass, nutrient, envelope radius, area radius), synchronous."""
+        out = torch.zeros(5, dtype=torch.float64, device="cuda")
+        self.diagnostics_device(out)
+        self.stream.synchronize()
+        return tuple(float(v) for v in out.cpu().numpy())
 
     def time(self):
         t, s = ctypes.c_double(), ctypes.c_int64()

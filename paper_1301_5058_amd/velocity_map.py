@@ -28,7 +28,8 @@ def window(side, h=1.0):
     return 4.0 * R0 * h, 0.8 * side * h / 2.0
 
 
-def solver_velocities(points, side, steps, seeds=(0,), tune=True, max_batch=1024):
+def solver_velocities(points, side, steps, seeds=(0,), tune=True, max_batch=1024,
+                      radius="area"):
     """Velocity of every (point, seed) pair: returns (v [m, len(seeds)], npts, gpu_seconds).
 
     gpu_seconds is the device time of the runs and fits (events on the batch
@@ -59,7 +60,7 @@ def solver_velocities(points, side, steps, seeds=(0,), tune=True, max_batch=1024
         torch.cuda.synchronize()
         e0.record(st)
         B.run(steps, SAMPLE_EVERY)
-        vv, nn = B.fit_velocity(lo, hi)
+        vv, nn = B.fit_velocity(lo, hi, radius=radius)
         e1.record(st)
         torch.cuda.synchronize()
         gpu_s += e0.elapsed_time(e1) / 1e3

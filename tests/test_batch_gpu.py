@@ -47,8 +47,7 @@ def _single(b, n, s, desc, steps, every, law="receptor"):
     diags = []
     for _ in range(steps // every):
         S.step(every)
-        t, _k = S.time()
-        diags.append((t,) + S.diagnostics())
+        diags.append(S.diagnostics_all())
     fb, fn = S.get_fields()
     S.close()
     return fb, fn, np.array(diags)
@@ -60,14 +59,13 @@ def test_batch_matches_single_instance_bitwise(law):
     B, fields, descs = _setup(INSTANCES, law=law, max_samples=64)
     B.run(steps, every)
     ser = B.series()
-    assert ser.shape == (len(INSTANCES), steps // every, 4)
+    assert ser.shape == (len(INSTANCES), steps // every, 5)
     for k, ((b, n, s), d) in enumerate(zip(fields, descs)):
         fb, fn, diags = _single(b, n, s, d, steps, every, law)
         gb, gn = B.get_fields(k)
         assert np.array_equal(gb, fb) and np.array_equal(gn, fn), k
-        assert np.array_equal(ser[k, :, 0], diags[:, 0])
+        assert np.array_equal(ser[k][:, [0, 3, 4]], diags[:, [0, 3, 4]])
         np.testing.assert_allclose(ser[k, :, 1:3], diags[:, 1:3], rtol=1e-13, atol=0)
-        assert np.array_equal(ser[k, :, 3], diags[:, 3])
     B.close()
 
 
@@ -89,7 +87,7 @@ def test_persistent_equals_per_block_launches_and_any_tuning():
             continue
         # fields, times and radii are exact; the double sums are folded per strip,
         # so another strip partition changes their rounding only
-        assert np.array_equal(got[0][..., [0, 3]], ref[0][..., [0, 3]]), tune
+        assert np.array_equal(got[0][..., [0, 3, 4]], ref[0][..., [0, 3, 4]]), tune
         np.testing.assert_allclose(got[0][..., 1:3], ref[0][..., 1:3], rtol=1e-13, atol=0)
         for (a, b_), (c, d) in zip(got[1], ref[1]):
             assert np.array_equal(a, c) and np.array_equal(b_, d), tune
@@ -104,9 +102,10 @@ def test_instance_matches_oracle():
     ob, on = oracle.run(b, n, s, 1.0, descs[0]["dt"], 400, chi=d["chi"])
     assert np.max(np.abs(gb - ob)) / np.max(ob) <= 1e-4
     assert np.max(np.abs(gn - on)) / np.max(on) <= 1e-4
-    m, nu, r = oracle.diag(ob, on, 1.0, descs[0]["b_thr"])
+    m, nu, r, ra = oracle.diag(ob, on, 1.0, descs[0]["b_thr"], area=True)
     ser = B.series()
     assert abs(ser[0, -1, 1] - m) / m <= 5e-3 and abs(ser[0, -1, 3] - r) <= max(1.0, 5e-3 * r)
+    assert abs(ser[0, -1, 4] - ra) <= 5e-3 * ra
     B.close()
 
 
@@ -116,13 +115,14 @@ def test_velocity_fit_equals_oracle_fit_of_same_series():
     B.run(3000, 100)
     ser = B.series()
     lo, hi = np.array([8.0, 8.0]), np.array([60.0, 60.0])
-    v, npts = B.fit_velocity(lo, hi)
-    for k in range(2):
-        vo, ko = oracle.fit_velocity(ser[k, :, 0], ser[k, :, 3], lo[k], hi[k])
-        assert npts[k] == ko and ko >= 3
-        assert v[k] == pytest.approx(vo, rel=1e-12)
-    # chemotaxis speeds the envelope up (abstract; Sec. 3.1; Sec. 4.1 eq. speedinq)
-    assert v[1] > v[0] > 0
+    for col, radius in ((3, "envelope"), (4, "area")):
+        v, npts = B.fit_velocity(lo, hi, radius=radius)
+        for k in range(2):
+            vo, ko = oracle.fit_velocity(ser[k, :, 0], ser[k, :, col], lo[k], hi[k])
+            assert npts[k] == ko and ko >= 3
+            assert v[k] == pytest.approx(vo, rel=1e-12)
+        # chemotaxis speeds the envelope up (abstract; Sec. 3.1; Sec. 4.1 eq. speedinq)
+        assert v[1] > v[0] > 0
     v2, n2 = B.fit_velocity(1e6, 2e6)
     assert np.all(np.isnan(v2)) and np.all(n2 == 0)
     B.close()
@@ -170,7 +170,7 @@ def test_batch_autotune_keeps_results():
     assert every % T == 0 and np.all(rows >= 1) and pf in (2, 4)
     B.run(steps, every)
     ser = B.series()
-    assert np.array_equal(ser[..., [0, 3]], ref[0][..., [0, 3]])
+    assert np.array_equal(ser[..., [0, 3, 4]], ref[0][..., [0, 3, 4]])
     np.testing.assert_allclose(ser[..., 1:3], ref[0][..., 1:3], rtol=1e-13, atol=0)
     for k in range(len(INSTANCES)):
         gb, gn = B.get_fields(k)

@@ -326,7 +326,8 @@ def test_diagnostics_by_hand():
     b[2, 3] = 1.0   # centre (cx, cy) = (3, 2): distance 0
     b[4, 6] = 0.6   # distance sqrt(9 + 4)
     b[0, 1] = 0.4   # below threshold
-    m, nu, r = oracle.diag(b, n, 0.5, 0.5)
+    m, nu, r, ra = oracle.diag(b, n, 0.5, 0.5, area=True)
+    assert ra == pytest.approx(0.5 * math.sqrt(2.0 / math.pi), rel=1e-15)  # two cells qualify
     assert m == pytest.approx(0.25 * 2.0, rel=1e-15)
     assert nu == pytest.approx(0.25 * 35 * 0.5, rel=1e-15)
     assert r == pytest.approx(0.5 * math.sqrt(13.0), rel=1e-15)

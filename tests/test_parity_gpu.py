@@ -168,15 +168,16 @@ def test_diagnostics_device_and_time():
     S = _solver(64, 48, 0.04, chi=0.5, h=0.5, b_thr=0.4, cx=10.0, cy=7.5)
     S.set_fields(b, n, s)
     S.step(37)
-    out = torch.zeros(8, dtype=torch.float64, device="cuda")
-    S.diagnostics_device(out[4:])
+    out = torch.zeros(10, dtype=torch.float64, device="cuda")
+    S.diagnostics_device(out[5:])
     torch.cuda.synchronize()
     gb, gn = S.get_fields()
-    m, nu, r = oracle.diag(gb, gn, 0.5, 0.4, cx=10.0, cy=7.5)
+    m, nu, r, ra = oracle.diag(gb, gn, 0.5, 0.4, cx=10.0, cy=7.5, area=True)
     o = out.cpu().numpy()
-    assert o[4] == 37 * 0.04
-    assert o[5] == pytest.approx(m, rel=1e-13) and o[6] == pytest.approx(nu, rel=1e-13)
-    assert o[7] == r
+    assert np.all(o[:5] == 0.0)
+    assert o[5] == 37 * 0.04
+    assert o[6] == pytest.approx(m, rel=1e-13) and o[7] == pytest.approx(nu, rel=1e-13)
+    assert o[8] == r and o[9] == ra and ra > 0
     S.close()
 
 
