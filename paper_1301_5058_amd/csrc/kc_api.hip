@@ -84,13 +84,16 @@ int check_params(const kc_params *p)
     return KC_OK;
 }
 
-// Default wavefront-strip height: about 2048 strips so the whole chip is busy.
+// Default wavefront-strip height: about 3000 strips (1.5 rounds of the 2048
+// wavefronts resident at two per SIMD), at least 8 and at most 96 rows.
 int default_rows(int precision, int tsteps, int nx, int ny)
 {
     const kc::StreamGeom g = kc::stream_geom(precision, tsteps, nx, ny, 1);
-    long rows = ((long)ny * g.nsx + 2047) / 2048;
+    long rows = ((long)ny * g.nsx + 2999) / 3000;
     if (rows < 8)
         rows = 8;
+    if (rows > 96)
+        rows = 96;
     return (int)rows;
 }
 
@@ -282,7 +285,7 @@ int kc_create(const kc_grid *g, double h, double dt, const kc_params *p, void *h
     c->esz = p->precision == KC_FP32 ? 4 : 8;
     c->stream = (hipStream_t)hip_stream;
     c->steps = p->step0;
-    c->tune.tsteps = p->precision == KC_FP32 ? 2 : 2;
+    c->tune.tsteps = 3; // fastest depth on gfx950 in both precisions (autotuner can change it)
     c->tune.prefetch = 4;
     c->tune.rows = default_rows(p->precision, c->tune.tsteps, c->nx, c->ny);
 
