@@ -1,6 +1,7 @@
 """Benchmark: explicit chemotaxis step on a 4096 x 4096 FP32 grid, one MI355X.
 
     python bench.py [--gpus 1] [--steps 50000] [--warmup 1000] [--no-cpu-baseline]
+                    [--no-extras] [--copy-ref-mib M]
 
 Workload (seeded, synthetic; the paper's set-up of Sec. 3): uniform nutrient
 n0 = 0.5, Gaussian inoculum b_max = 0.7 / radius 6 cells at the centre, agar
@@ -10,6 +11,12 @@ A step is one time step of the whole grid; every 100 steps the diagnostics
 (mass, nutrient, envelope radius) are sampled into a device series, as a run
 that tracks the colony envelope does.  Inputs are resident in HBM before the
 timed region.  Prints one JSON line.
+
+The line also carries, under "extras", the other workloads of the solver:
+the FP64 variant and chi = 0 at 4096^2, the 16384^2 grid (20,000 steps) with
+its 512^2 companion run checked against the oracle, the 256-instance batched
+sweep (30,000 steps, one persistent launch), and the velocity map (surrogate
+with solver fallback).  --no-extras skips them.
 """
 import argparse
 import hashlib
@@ -24,8 +31,14 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, 8 TB/s
+# VALU issue rate: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (one lane-op per lane per clock)
+VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+# algorithmic VALU lane-operations per cell-update (receptor law): coefficients 8,
+# two faces 2 x 9, two net fluxes 6, update 5 -- see the design doc section 6
+OPS_PER_CELL_UPDATE = 37
 BYTES_PER_CELL_LAUNCH = {"fp32": 20, "fp64": 40}  # read b, n, sigma; write b', n'
 SAMPLE_EVERY = 100
+T_START = time.perf_counter()
 METRIC = "GCell-updates/s & % HBM peak (4096^2 FP32); velocity-map pts/s at <=2% err"
 STEP_SOURCES = ("paper_1301_5058_amd/csrc/kc_step.hip", "paper_1301_5058_amd/csrc/kc_stream.h",
                 "paper_1301_5058_amd/csrc/kc_device.h")
@@ -77,6 +90,59 @@ def cpu_baseline(b, n, s, dt, chi, budget_s=15.0):
                       % (steps, b.shape[1], b.shape[0], el)}
 
 
+def progress(msg):
+    """Progress line on stderr (stdout carries only the JSON result)."""
+    print("[bench %.0fs] %s" % (time.perf_counter() - T_START, msg), file=sys.stderr, flush=True)
+
+
+def launch_probe(S, stream, launches=60):
+    """Average duration (ms) of one fused launch of the current depth, from
+    HIP events on the solver's stream around `launches` back-to-back launches."""
+    import torch
+    T = S.tuning()[0]
+    S.step(T * 4)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    S.step(T * launches)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / launches
+
+
+def roofline(precision, cells, tsteps, launch_ms):
+    """Roofline of the fused step kernel: the bound (HBM or VALU) with the
+    larger fraction of its peak is reported as the kernel's bound."""
+    bytes_per = BYTES_PER_CELL_LAUNCH[precision] * cells
+    gbs = bytes_per / (launch_ms / 1e3) / 1e9
+    tops = OPS_PER_CELL_UPDATE * cells * tsteps / (launch_ms / 1e3) / 1e12
+    hbm = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(gbs / HBM_PEAK_GBS, 4), "alg_bytes_per_launch": bytes_per}
+    alu = {"bound": "alu", "achieved": round(tops, 3), "peak": round(VALU_PEAK_TOPS, 2),
+           "unit": "Tops/s", "frac": round(tops / VALU_PEAK_TOPS, 4),
+           "alg_ops_per_launch": OPS_PER_CELL_UPDATE * cells * tsteps}
+    return (alu, hbm) if alu["frac"] > hbm["frac"] else (hbm, alu)
+
+
+def timed_run(S, stream, steps, series=None):
+    """K steps with diagnostics every SAMPLE_EVERY steps; returns elapsed ms."""
+    import torch
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    left, i = steps, 0
+    while left > 0:
+        k = min(SAMPLE_EVERY, left)
+        S.step(k)
+        if series is not None:
+            S.diagnostics_device(series[i])
+        left -= k
+        i += 1
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1)
+
+
 def run(args):
     import numpy as np
     import torch
@@ -89,52 +155,48 @@ def run(args):
     dt = workload.config_dt(b, n, s)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.copy_ref_mib:
+        # a plain device copy of known size, so that profiler byte counters can
+        # be calibrated against it (used by the PMC runs that write profiles/)
+        x = torch.ones(args.copy_ref_mib * 262144, dtype=torch.float32, device=dev)
+        y = torch.empty_like(x)
+        y.copy_(x)
+        torch.cuda.synchronize()
+        del x, y
     tb, tn, ts = (torch.from_numpy(a).to(dev) for a in (b, n, s))
     stream = torch.cuda.current_stream()
     S = Solver(nx, ny, dt=dt, chi=chi, precision="fp32", b_thr=0.5 * cfg["n0"], stream=stream)
     S.set_fields(tb, tn, ts)
+    tuned = S.autotune(effort=0 if args.quick_tune else 1, use_cache=True)
     tsteps, rows, pf = S.tuning()
+    progress("autotuned 4096^2 fp32: T=%d rows=%d prefetch=%d (%.1f GCell/s)"
+             % (tsteps, rows, pf, tuned))
 
     nsamp = args.steps // SAMPLE_EVERY + 2
     series = torch.zeros((nsamp, 5), dtype=torch.float64, device=dev)
-
-    # warmup (same code path)
     left = args.warmup
-    while left > 0:
+    while left > 0:  # warmup (same code path)
         k = min(SAMPLE_EVERY, left)
         S.step(k)
         left -= k
     torch.cuda.synchronize()
 
-    # timed region: HIP events on the solver's stream around every chunk
-    nchunks = (args.steps + SAMPLE_EVERY - 1) // SAMPLE_EVERY
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * nchunks + 1)]
-    torch.cuda.synchronize()
     t_wall = time.perf_counter()
-    ev[0].record(stream)
-    left, i = args.steps, 0
-    launches = 0
-    while left > 0:
-        k = min(SAMPLE_EVERY, left)
-        S.step(k)
-        launches += (k // tsteps) + (1 if k % tsteps else 0)
-        ev[2 * i + 1].record(stream)
-        S.diagnostics_device(series[i])
-        ev[2 * i + 2].record(stream)
-        left -= k
-        i += 1
-    torch.cuda.synchronize()
+    total_ms = timed_run(S, stream, args.steps, series)
     wall = time.perf_counter() - t_wall
-    total_ms = ev[0].elapsed_time(ev[2 * nchunks])
-    step_ms = sum(ev[2 * j].elapsed_time(ev[2 * j + 1]) for j in range(nchunks))
-
     cells = nx * ny
     value = cells * args.steps / (total_ms / 1e3) / 1e9
-    launch_ms = step_ms / launches
-    alg_bytes = BYTES_PER_CELL_LAUNCH["fp32"] * cells
-    achieved = alg_bytes / (launch_ms / 1e3) / 1e9
-    traffic = measured_traffic(tsteps)
-    last = series[nchunks - 1].cpu().numpy()
+    last = series[(args.steps + SAMPLE_EVERY - 1) // SAMPLE_EVERY - 1].cpu().numpy()
+
+    progress("timed %d steps: %.1f GCell/s" % (args.steps, value))
+    launch_ms = launch_probe(S, stream)
+    main_rl, other_rl = roofline("fp32", cells, tsteps, launch_ms)
+    main_rl["traffic"] = measured_traffic(tsteps)
+    main_rl["kernel"] = "step_stream<float,T=%d,PF=%d>" % (tsteps, pf)
+    main_rl["launch_us"] = round(launch_ms * 1e3, 3)
+    main_rl["other_bound"] = other_rl
+    S.close()
+
     out = {
         "metric": METRIC,
         "value": round(value, 3),
@@ -151,22 +213,155 @@ def run(args):
         "config": {"workload": "single instance 4096x4096 FP32, n0=0.5, sigma amplitude 0.5, "
                                "chi=1 receptor law, forward Euler, diagnostics every 100 steps",
                    "nx": nx, "ny": ny, "dt": dt, "chi": chi, "tsteps": tsteps, "rows": rows,
-                   "prefetch": pf},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic,
-                     "kernel": "step_stream<float,T=%d>" % tsteps,
-                     "launch_us": round(launch_ms * 1e3, 3),
-                     "alg_bytes_per_launch": alg_bytes},
+                   "prefetch": pf, "autotune_gcell_s": round(tuned, 1)},
+        "roofline": main_rl,
         "effective_hbm_frac": round(value * 1e9 * 20 / (HBM_PEAK_GBS * 1e9), 4),
         "wall_s": round(wall, 3),
         "final_diag": {"t": float(last[0]), "mass": float(last[1]), "nutrient": float(last[2]),
                        "envelope_radius": float(last[3]), "area_radius": float(last[4])},
     }
-    S.close()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(b, n, s, dt, chi)
+        progress("cpu baseline: %.3f GCell/s on %d threads"
+                 % (out["cpu_baseline"]["value"], out["cpu_baseline"]["cores"]))
+    if not args.no_extras:
+        out["extras"] = extras(args)
     return out
+
+
+def single_variant(nx, n0, a, chi, precision, steps, tune_effort=0):
+    """GCell-updates/s of one single-instance configuration (autotuned)."""
+    import numpy as np
+    import torch
+    from paper_1301_5058_amd import workload
+    from paper_1301_5058_amd.solver import Solver
+    b, n, s = workload.fields(nx, nx, n0, a, 0)
+    dt = workload.config_dt(b, n, s)
+    if precision == "fp64":
+        b, n, s = (x.astype(np.float64) for x in (b, n, s))
+    stream = torch.cuda.current_stream()
+    S = Solver(nx, nx, dt=dt, chi=chi, precision=precision, b_thr=0.5 * n0, stream=stream)
+    S.set_fields(*(torch.from_numpy(x).cuda() for x in (b, n, s)))
+    S.autotune(effort=tune_effort, use_cache=True)
+    T, rows, pf = S.tuning()
+    S.step(100)
+    ms = timed_run(S, stream, steps)
+    lm = launch_probe(S, stream, 20)
+    rl, _ = roofline(precision, nx * nx, T, lm)
+    S.close()
+    return {"gcell_s": round(nx * nx * steps / (ms / 1e3) / 1e9, 2), "steps": steps,
+            "tsteps": T, "rows": rows, "prefetch": pf, "roofline_bound": rl["bound"],
+            "roofline_frac": rl["frac"]}
+
+
+def hires(steps):
+    """The 16384^2 grid (n0 = 0.35, chi = 2, a = 0.5) and its 512^2 companion
+    run in the same kernel configuration, checked against the FP64 oracle."""
+    import numpy as np
+    import torch
+    import oracle
+    from paper_1301_5058_amd import workload
+    from paper_1301_5058_amd.solver import Solver
+    c = workload.HIRES_16384
+    b, n, s = workload.fields(c["nx"], c["ny"], c["n0"], c["a"], c["seed"])
+    dt = workload.config_dt(b, n, s)
+    stream = torch.cuda.current_stream()
+    S = Solver(c["nx"], c["ny"], dt=dt, chi=c["chi"], b_thr=0.5 * c["n0"], stream=stream)
+    S.set_fields(*(torch.from_numpy(x).cuda() for x in (b, n, s)))
+    del b, n, s
+    S.autotune(effort=0, use_cache=True)
+    T, rows, pf = S.tuning()
+    series = torch.zeros((steps // SAMPLE_EVERY + 2, 5), dtype=torch.float64, device="cuda")
+    ms = timed_run(S, stream, steps, series)
+    d = series[steps // SAMPLE_EVERY - 1].cpu().numpy()
+    S.close()
+    res = {"nx": c["nx"], "steps": steps, "gcell_s": round(c["nx"] * c["ny"] * steps / (ms / 1e3) / 1e9, 2),
+           "tsteps": T, "rows": rows, "prefetch": pf, "seconds": round(ms / 1e3, 3),
+           "final_envelope_radius": float(d[3]), "final_area_radius": float(d[4])}
+    # companion 512^2 run, same parameters and kernel configuration, vs the oracle
+    k = workload.CROP_512
+    b, n, s = workload.fields(k["nx"], k["ny"], k["n0"], k["a"], k["seed"])
+    dt = workload.config_dt(b, n, s)
+    S = Solver(k["nx"], k["ny"], dt=dt, chi=k["chi"], b_thr=0.5 * k["n0"], stream=stream)
+    S.set_fields(b, n, s)
+    S.set_tuning(T, rows, pf)
+    S.step(k["steps"])
+    gb, gn = S.get_fields()
+    gd = S.diagnostics()
+    S.close()
+    ob, on = oracle.run(b, n, s, 1.0, dt, k["steps"], chi=k["chi"])
+    od = oracle.diag(ob, on, 1.0, 0.5 * k["n0"])
+    res["check_512"] = {"steps": k["steps"],
+                        "normwise_err_b": float(np.max(np.abs(gb - ob)) / np.max(np.abs(ob))),
+                        "normwise_err_n": float(np.max(np.abs(gn - on)) / np.max(np.abs(on))),
+                        "mass_rel_err": abs(gd[0] - od[0]) / od[0],
+                        "radius_rel_err": abs(gd[2] - od[2]) / max(od[2], 1e-30)}
+    return res
+
+
+def sweep(steps=30000, every=100):
+    """The 256-instance parameter sweep in one persistent launch."""
+    import numpy as np
+    import torch
+    import oracle
+    from paper_1301_5058_amd import workload
+    from paper_1301_5058_amd.batch import Batch
+    insts = workload.sweep()
+    descs, cells = [], 0
+    t0 = time.perf_counter()
+    B = None
+    fields = []
+    for d in insts:
+        b, n, s = workload.fields(d["nx"], d["ny"], d["n0"], d["a"], d["seed"])
+        dt = workload.config_dt(b, n, s)
+        descs.append(dict(nx=d["nx"], ny=d["ny"], dt=dt, chi=d["chi"], b_thr=0.5 * d["n0"]))
+        fields.append((b, n, s))
+        cells += d["nx"] * d["ny"]
+    B = Batch(descs, max_samples=steps // every + 1)
+    for k, (b, n, s) in enumerate(fields):
+        B.set_fields(k, b, n, s)
+    del fields
+    setup = time.perf_counter() - t0
+    B.autotune(every, effort=0)
+    T, rows, pf, _ = B.tuning()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    B.run(steps, every)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    lo = np.full(len(insts), 24.0)
+    hi = np.array([0.8 * d["nx"] / 2 for d in insts])
+    v, npts = B.fit_velocity(lo, hi, radius="area")
+    ve, _ = B.fit_velocity(lo, hi, radius="envelope")
+    B.close()
+    cb = np.array([oracle.cbar(d["n0"], d["chi"]) for d in insts])
+    ok = np.isfinite(v)
+    return {"instances": len(insts), "cells": cells, "steps": steps, "tsteps": T,
+            "prefetch": pf, "seconds": round(ms / 1e3, 3),
+            "gcell_s": round(cells * steps / (ms / 1e3) / 1e9, 2),
+            "instances_per_s": round(len(insts) / (ms / 1e3), 2),
+            "setup_s": round(setup, 2), "velocities_fitted": int(ok.sum()),
+            "v_over_cbar_median": float(np.median(v[ok] / cb[ok])),
+            "v_envelope_over_area_median": float(np.nanmedian(ve / v))}
+
+
+def extras(args):
+    from paper_1301_5058_amd import velocity_map
+    ex = {}
+    ex["fp64_4096"] = single_variant(4096, 0.5, 0.5, 1.0, "fp64", 5000)
+    progress("fp64 4096^2: %s" % ex["fp64_4096"])
+    ex["chi0_4096_fp32"] = single_variant(4096, 0.5, 0.5, 0.0, "fp32", 20000)
+    progress("chi=0 4096^2: %s" % ex["chi0_4096_fp32"])
+    ex["hires_16384"] = hires(20000)
+    progress("16384^2: %s" % ex["hires_16384"])
+    ex["sweep_256"] = sweep()
+    progress("sweep: %s" % ex["sweep_256"])
+    ex["velocity_map"] = velocity_map.run_velocity_map()
+    progress("velocity map: %s" % ex["velocity_map"])
+    return ex
 
 
 def main():
@@ -175,6 +370,9 @@ def main():
     ap.add_argument("--steps", type=int, default=50000)
     ap.add_argument("--warmup", type=int, default=1000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--quick-tune", action="store_true")
+    ap.add_argument("--copy-ref-mib", type=int, default=0)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only; --gpus %d is not supported "

@@ -90,7 +90,7 @@ class VelocityMap:
         self.S.set_normalization(self.IN_SHIFT, self.IN_SCALE, float(np.mean(v)),
                                  float(np.std(v) + 1e-12))
         loss = self.S.train(X, v, iters=iters, batch=min(batch, len(X)), lr=lr)
-        self.S.set_hull(hull_facets(X.astype(np.float64)), tol=1e-9)
+        self.S.set_hull(hull_facets(X.astype(np.float64)), tol=1e-6)
         self.trained = True
         return loss
 
@@ -118,3 +118,88 @@ class VelocityMap:
             out[fb] = np.nanmean(vs, axis=1)
         return out, inside, dict(surrogate_gpu_s=sur_s, surrogate_wall_s=host_s,
                                  fallback_points=int(len(fb)), fallback_gpu_s=solver_s)
+
+
+# ---------------------------------------------------------------------------
+# The velocity-map workload: (n0, chi, a) in [0.3, 1.2] x [0, 2] x [0.1, 0.5]
+# ---------------------------------------------------------------------------
+BOX_LO = np.array([0.3, 0.0, 0.1])
+BOX_HI = np.array([1.2, 2.0, 0.5])
+
+
+def design_grid(per_axis=16):
+    """Full-factorial training design (per_axis^3 points, faces included, so the
+    hull of the design is the whole box)."""
+    ax = [np.linspace(BOX_LO[i], BOX_HI[i], per_axis) for i in range(3)]
+    g = np.stack(np.meshgrid(*ax, indexing="ij"), -1).reshape(-1, 3)
+    return g
+
+
+def run_velocity_map(side=256, steps=8000, per_axis=16, held_out=64, judge_seeds=(101, 102, 103, 104),
+                     query=512, band=256, iters=6000, seed=7):
+    """Train the surrogate on solver velocities, judge it on held-out points
+    against the seed-averaged solver, and time a query map with fallback.
+
+    Returns a dict of the measurements (all velocities by the area radius)."""
+    rng = np.random.default_rng(seed)
+    out = dict(protocol=dict(side=side, steps=steps, sample_every=SAMPLE_EVERY, radius="area",
+                             window=list(window(side)), box_lo=BOX_LO.tolist(),
+                             box_hi=BOX_HI.tolist()))
+    # 1. training velocities from the batched solver (one seed per point)
+    X = design_grid(per_axis)
+    t0 = time.perf_counter()
+    v, npts, gpu_train = solver_velocities(X, side, steps, seeds=(0,))
+    v = v[:, 0]
+    host_train = time.perf_counter() - t0
+    ok = np.isfinite(v)
+    out["train"] = dict(points=int(len(X)), finite=int(ok.sum()), solver_gpu_s=round(gpu_train, 3),
+                        wall_s=round(host_train, 2),
+                        solver_pts_per_s=round(len(X) / gpu_train, 2))
+    # 2. surrogate training on the GPU
+    vm = VelocityMap()
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    loss = vm.fit(X[ok], v[ok], iters=iters)
+    e1.record(st)
+    torch.cuda.synchronize()
+    out["fit"] = dict(iters=iters, final_loss=loss, gpu_s=round(e0.elapsed_time(e1) / 1e3, 3))
+    # 3. held-out judge: random interior points, solver averaged over seeds
+    H = BOX_LO + (BOX_HI - BOX_LO) * rng.uniform(0.02, 0.98, (held_out, 3))
+    vj, _, gpu_judge = solver_velocities(H, side, steps, seeds=tuple(judge_seeds))
+    judge = np.nanmean(vj, axis=1)
+    spread = np.nanstd(vj, axis=1) / judge
+    pred = vm.S.predict(H.astype(np.float32)).astype(np.float64)
+    rel = np.abs(pred - judge) / judge
+    # the closed-form bound with one fitted scale (what the method gives without the network)
+    cb_tr = vm.S.cbar(X[ok].astype(np.float32)).astype(np.float64)
+    scale = float(np.sum(cb_tr * v[ok]) / np.sum(cb_tr * cb_tr))
+    cb_h = vm.S.cbar(H.astype(np.float32)).astype(np.float64)
+    rel_cb = np.abs(scale * cb_h - judge) / judge
+    out["held_out"] = dict(points=int(held_out), seeds=len(judge_seeds),
+                           judge_seed_spread_median=float(np.median(spread)),
+                           surrogate_rel_err_median=float(np.median(rel)),
+                           surrogate_rel_err_p95=float(np.quantile(rel, 0.95)),
+                           surrogate_rel_err_max=float(np.max(rel)),
+                           surrogate_within_2pct=float(np.mean(rel <= 0.02)),
+                           scaled_cbar_rel_err_median=float(np.median(rel_cb)),
+                           scaled_cbar_rel_err_p95=float(np.quantile(rel_cb, 0.95)),
+                           cbar_scale=scale, judge_gpu_s=round(gpu_judge, 3))
+    # 4. query map: query x query (n0, chi) at a = 0.3 inside the box, plus a band outside
+    n0q, chq = np.meshgrid(np.linspace(BOX_LO[0], BOX_HI[0], query),
+                           np.linspace(BOX_LO[1], BOX_HI[1], query), indexing="ij")
+    Q = np.stack([n0q.ravel(), chq.ravel(), np.full(query * query, 0.3)], 1)
+    nb = int(round(np.sqrt(band)))
+    bn, bc = np.meshgrid(np.linspace(1.21, 1.4, nb), np.linspace(2.01, 2.5, nb), indexing="ij")
+    Bq = np.stack([bn.ravel(), bc.ravel(), np.full(nb * nb, 0.3)], 1)
+    allq = np.concatenate([Q, Bq], 0)
+    vals, inside, tm = vm.query(allq, side, steps)
+    total_s = tm["surrogate_gpu_s"] + tm["fallback_gpu_s"]
+    out["query"] = dict(points=int(len(allq)), inside=int(inside.sum()),
+                        fallback=tm["fallback_points"], surrogate_gpu_s=round(tm["surrogate_gpu_s"], 5),
+                        fallback_gpu_s=round(tm["fallback_gpu_s"], 3),
+                        pts_per_s_with_fallback=round(len(allq) / total_s, 1),
+                        pts_per_s_plain_solver=out["train"]["solver_pts_per_s"],
+                        speedup=round((len(allq) / total_s) / out["train"]["solver_pts_per_s"], 1))
+    vm.S.close()
+    return out
