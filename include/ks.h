@@ -12,9 +12,11 @@
  * layer, weights and hidden activations rounded to bfloat16, every product
  * accumulated in float32 (the two 64 x 64 layers and their gradients on
  * MFMA).  Inputs and targets pass through caller-chosen affine maps:
- *   x' = (x - in_shift) / in_scale,   v = v' * out_scale + out_shift.
- * Training minimises the mean squared error of v' against the mapped targets
- * with Adam (float32 master weights and moments).
+ *   x' = (x - in_shift) / in_scale,   v = v' * out_scale + out_shift,
+ * or, in log-target mode, v = exp(v' * out_scale + out_shift) (targets y are
+ * mapped as (log y - out_shift) / out_scale, so the loss weighs relative
+ * errors).  Training minimises the mean squared error of v' against the
+ * mapped targets with Adam (float32 master weights and moments).
  *
  * Parameter vector (float32, 8641 entries, row-major [out][in] weights):
  *   W1[64][3] b1[64] W2[64][64] b2[64] W3[64][64] b3[64] W4[64] b4
@@ -47,9 +49,10 @@ int ks_create(int32_t max_points, void *hip_stream, ks_model **out);
 int ks_set_params(ks_model *m, const float *params);
 int ks_get_params(ks_model *m, float *params);
 
-/* Affine maps of inputs (3 shifts, 3 non-zero scales) and of the output. */
+/* Affine maps of inputs (3 shifts, 3 non-zero scales) and of the output;
+ * log_target 1 selects log-target mode (targets must then be > 0). */
 int ks_set_normalization(ks_model *m, const double *in_shift, const double *in_scale,
-                         double out_shift, double out_scale);
+                         double out_shift, double out_scale, int32_t log_target);
 
 /* iters Adam steps (learning rate lr > 0, beta1 0.9, beta2 0.999, eps 1e-8)
  * on minibatches of `batch` consecutive points, cycling through the n points.

@@ -60,8 +60,9 @@ def _maps(in_shift, in_scale):
 
 
 def forward(params, X, in_shift=(0, 0, 0), in_scale=(1, 1, 1), out_shift=0.0, out_scale=1.0,
-            emulate_bf16=True):
-    """Predicted v (target units) for X [n, 3]; also returns the cache for backward."""
+            emulate_bf16=True, log_target=False):
+    """Predicted v (target units) for X [n, 3]; also returns the cache for backward.
+    With log_target the output map is v = exp(v' scale + shift)."""
     P = unpack(params)
     rnd = bf16 if emulate_bf16 else (lambda a: np.asarray(a, np.float64))
     sh, sc = _maps(in_shift, in_scale)
@@ -75,16 +76,19 @@ def forward(params, X, in_shift=(0, 0, 0), in_scale=(1, 1, 1), out_shift=0.0, ou
     h3 = rnd(gelu(z3))
     vp = h3 @ W4 + P["b4"]
     cache = dict(x=x, z1=z1, h1=h1, z2=z2, h2=h2, z3=z3, h3=h3, vp=vp, W2=W2, W3=W3, W4=W4)
-    return vp * out_scale + out_shift, cache
+    o = vp * out_scale + out_shift
+    return (np.exp(o) if log_target else o), cache
 
 
 def loss_and_grad(params, X, y, in_shift=(0, 0, 0), in_scale=(1, 1, 1), out_shift=0.0,
-                  out_scale=1.0, emulate_bf16=True):
-    """(loss in mapped units, gradient [8641]) of the mean squared error."""
+                  out_scale=1.0, emulate_bf16=True, log_target=False):
+    """(loss in mapped units, gradient [8641]) of the mean squared error; with
+    log_target the targets are mapped as (log y - shift) / scale."""
     rnd = bf16 if emulate_bf16 else (lambda a: np.asarray(a, np.float64))
     _, C = forward(params, X, in_shift, in_scale, out_shift, out_scale, emulate_bf16)
     n = len(C["vp"])
-    yt = (np.asarray(y, np.float64) - out_shift) / out_scale
+    yv = np.asarray(y, np.float64)
+    yt = ((np.log(yv) if log_target else yv) - out_shift) / out_scale
     e = C["vp"] - yt
     loss = float(np.mean(e * e))
     dv = 2.0 * e / n

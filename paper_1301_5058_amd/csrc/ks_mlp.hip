@@ -83,7 +83,8 @@ struct MlpArgs {
     int ntot;
     float in_shift[3], in_inv[3];
     float out_shift, out_scale, out_inv;
-    float inv_b; // 1 / n (mean of the squared error)
+    int log_target; // targets and outputs in log space: v = exp(v' scale + shift)
+    float inv_b;    // 1 / n (mean of the squared error)
     float *gpart; // [waves][NP]
     float *lpart; // [waves]
 };
@@ -239,8 +240,10 @@ __global__ __launch_bounds__(256) void mlp_kernel(MlpArgs a)
             if (c == 0) {
 #pragma unroll
                 for (int r = 0; r < 4; ++r)
-                    if (valid[r])
-                        a.v[idx[r]] = vp[r] * a.out_scale + a.out_shift;
+                    if (valid[r]) {
+                        const float o = vp[r] * a.out_scale + a.out_shift;
+                        a.v[idx[r]] = a.log_target ? expf(o) : o;
+                    }
             }
             continue;
         }
@@ -248,7 +251,10 @@ __global__ __launch_bounds__(256) void mlp_kernel(MlpArgs a)
         float dv[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const float yt = valid[r] ? (a.y[idx[r]] - a.out_shift) * a.out_inv : 0.f;
+            float yv = valid[r] ? a.y[idx[r]] : 1.f;
+            if (a.log_target)
+                yv = logf(yv);
+            const float yt = valid[r] ? (yv - a.out_shift) * a.out_inv : 0.f;
             const float e = valid[r] ? vp[r] - yt : 0.f;
             dv[r] = 2.0f * e * a.inv_b;
             if (c == 0) {
@@ -404,6 +410,13 @@ __global__ __launch_bounds__(256) void adam_reduce(float *params, float *m1, flo
     }
 }
 
+__global__ void fill_zero(float *p, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n)
+        p[i] = 0.f;
+}
+
 __global__ void hull_test(const float *X, int n, const double *facets, int nf, double tol,
                           unsigned char *inside)
 {
@@ -447,6 +460,7 @@ struct ks_model {
     int nf = 0;
     double tol = 0;
     double in_shift[3] = {0, 0, 0}, in_scale[3] = {1, 1, 1}, out_shift = 0, out_scale = 1;
+    int log_target = 0;
     long long t = 0;
     int maxwaves = 256;
     std::string err;
@@ -491,6 +505,7 @@ ks::MlpArgs base_args(const ks_model *m)
     a.out_shift = (float)m->out_shift;
     a.out_scale = (float)m->out_scale;
     a.out_inv = (float)(1.0 / m->out_scale);
+    a.log_target = m->log_target;
     a.inv_b = 1.f;
     a.gpart = m->gpart;
     a.lpart = m->lpart;
@@ -628,8 +643,11 @@ int ks_set_params(ks_model *m, const float *params)
             return kfail(m, KC_ENONFINITE, "parameter %d is not finite", i);
     KS_HIP(m, hipMemcpyAsync(m->params, params, ks::NP * sizeof(float), hipMemcpyHostToDevice,
                              m->stream));
-    KS_HIP(m, hipMemsetAsync(m->m1, 0, ks::NP * sizeof(float), m->stream));
-    KS_HIP(m, hipMemsetAsync(m->m2, 0, ks::NP * sizeof(float), m->stream));
+    hipLaunchKernelGGL(ks::fill_zero, dim3((ks::NP + 255) / 256), dim3(256), 0, m->stream, m->m1,
+                       ks::NP);
+    hipLaunchKernelGGL(ks::fill_zero, dim3((ks::NP + 255) / 256), dim3(256), 0, m->stream, m->m2,
+                       ks::NP);
+    KS_HIP(m, hipGetLastError());
     KS_HIP(m, hipStreamSynchronize(m->stream));
     m->t = 0;
     return KC_OK;
@@ -646,7 +664,7 @@ int ks_get_params(ks_model *m, float *params)
 }
 
 int ks_set_normalization(ks_model *m, const double *in_shift, const double *in_scale,
-                         double out_shift, double out_scale)
+                         double out_shift, double out_scale, int32_t log_target)
 {
     if (!m || !in_shift || !in_scale)
         return KC_EINVAL;
@@ -659,8 +677,11 @@ int ks_set_normalization(ks_model *m, const double *in_shift, const double *in_s
         m->in_shift[j] = in_shift[j];
         m->in_scale[j] = in_scale[j];
     }
+    if (log_target != 0 && log_target != 1)
+        return kfail(m, KC_EINVAL, "log_target must be 0 or 1");
     m->out_shift = out_shift;
     m->out_scale = out_scale;
+    m->log_target = log_target;
     return KC_OK;
 }
 

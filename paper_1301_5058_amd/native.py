@@ -84,7 +84,8 @@ _SIGS = {
     "ks_create": (c_int32, [c_int32, c_void_p, ctypes.POINTER(c_void_p)]),
     "ks_set_params": (c_int32, [c_void_p, c_void_p]),
     "ks_get_params": (c_int32, [c_void_p, c_void_p]),
-    "ks_set_normalization": (c_int32, [c_void_p, c_void_p, c_void_p, c_double, c_double]),
+    "ks_set_normalization": (c_int32, [c_void_p, c_void_p, c_void_p, c_double, c_double,
+                                       c_int32]),
     "ks_train": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, c_int32, c_int32, c_double,
                            c_int32, P_double]),
     "ks_grad": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, c_void_p, P_double, c_int32]),

@@ -71,13 +71,14 @@ class Surrogate:
         self._chk(N.lib().ks_get_params(self.h, p.ctypes.data_as(ctypes.c_void_p)))
         return p
 
-    def set_normalization(self, in_shift, in_scale, out_shift, out_scale):
+    def set_normalization(self, in_shift, in_scale, out_shift, out_scale, log_target=False):
         a = np.ascontiguousarray(in_shift, dtype=np.float64)
         b = np.ascontiguousarray(in_scale, dtype=np.float64)
-        self.norm = (a.copy(), b.copy(), float(out_shift), float(out_scale))
+        self.norm = (a.copy(), b.copy(), float(out_shift), float(out_scale), bool(log_target))
         self._chk(N.lib().ks_set_normalization(self.h, a.ctypes.data_as(ctypes.c_void_p),
                                                b.ctypes.data_as(ctypes.c_void_p),
-                                               float(out_shift), float(out_scale)))
+                                               float(out_shift), float(out_scale),
+                                               1 if log_target else 0))
 
     def train(self, X, v, iters, batch, lr):
         X = self._x(X)

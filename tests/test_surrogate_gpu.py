@@ -10,10 +10,11 @@ pytestmark = pytest.mark.gpu
 MAPS = dict(in_shift=(0.75, 1.0, 0.3), in_scale=(0.45, 1.0, 0.2), out_shift=0.3, out_scale=0.2)
 
 
-def _model(maxp=70000, seed=0):
+def _model(maxp=70000, seed=0, log_target=False):
     from paper_1301_5058_amd.surrogate import Surrogate, he_uniform
     S = Surrogate(maxp)
-    S.set_normalization(MAPS["in_shift"], MAPS["in_scale"], MAPS["out_shift"], MAPS["out_scale"])
+    S.set_normalization(MAPS["in_shift"], MAPS["in_scale"], MAPS["out_shift"], MAPS["out_scale"],
+                        log_target=log_target)
     p = he_uniform(seed)
     rng = np.random.default_rng(seed + 100)
     p[192:256] = rng.uniform(-0.2, 0.2, 64)     # non-zero biases exercise every term
@@ -46,6 +47,20 @@ def test_gradient_matches_reference(n):
         err = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
         print("%s rel err %.2e" % (name, err))
         assert err <= 2e-2, name
+    S.close()
+
+
+def test_log_target_mode_matches_reference():
+    S, p = _model(log_target=True)
+    X, y = _data(777, 6)
+    g, loss = S.grad(X, y)
+    lr, gr = mlp_ref.loss_and_grad(p.astype(np.float64), X.astype(np.float64), y, log_target=True,
+                                   **MAPS)
+    assert loss == pytest.approx(lr, rel=2e-3)
+    assert np.linalg.norm(g - gr) <= 2e-2 * np.linalg.norm(gr)
+    v = S.predict(X)
+    vr, _ = mlp_ref.forward(p.astype(np.float64), X.astype(np.float64), log_target=True, **MAPS)
+    assert np.max(np.abs(v - vr) / vr) <= 1e-2 * MAPS["out_scale"] * 5
     S.close()
 
 
