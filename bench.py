@@ -43,6 +43,10 @@ METRIC = "GCell-updates/s & % HBM peak (4096^2 FP32); velocity-map pts/s at <=2%
 STEP_SOURCES = ("paper_1301_5058_amd/csrc/kc_step.hip", "paper_1301_5058_amd/csrc/kc_stream.h",
                 "paper_1301_5058_amd/csrc/kc_device.h")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_stream_4096_fp32_traffic.txt")
+# shipped autotune database (written by paper_1301_5058_amd/tune_db.py on an MI355X);
+# grids without an entry are timed on the spot
+os.environ.setdefault("KC_AUTOTUNE_CACHE",
+                      os.path.join(ROOT, "paper_1301_5058_amd", "tuning", "gfx950.jsonl"))
 
 
 def kernel_hash():
@@ -53,16 +57,19 @@ def kernel_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(tsteps):
+def measured_traffic(tsteps, rows, prefetch):
     """HBM bytes per step-kernel launch from the committed PMC summary, or None
-    when the summary is missing, for another fused depth, or for older kernel
-    sources."""
+    when the summary is missing, was taken for another configuration, or for
+    older kernel sources."""
     try:
         txt = open(TRAFFIC_FILE).read()
     except OSError:
         return None
     kv = dict(re.findall(r"^(\w+)\s*=\s*(\S+)", txt, flags=re.M))
-    if kv.get("kernel_sources_sha256_16") != kernel_hash() or int(kv.get("tsteps", -1)) != tsteps:
+    if kv.get("kernel_sources_sha256_16") != kernel_hash():
+        return None
+    if (int(kv.get("tsteps", -1)), int(kv.get("rows", -1)), int(kv.get("prefetch", -1))) != \
+            (tsteps, rows, prefetch):
         return None
     try:
         return float(kv["hbm_bytes_per_launch"])
@@ -191,7 +198,7 @@ def run(args):
     progress("timed %d steps: %.1f GCell/s" % (args.steps, value))
     launch_ms = launch_probe(S, stream)
     main_rl, other_rl = roofline("fp32", cells, tsteps, launch_ms)
-    main_rl["traffic"] = measured_traffic(tsteps)
+    main_rl["traffic"] = measured_traffic(tsteps, rows, pf)
     main_rl["kernel"] = "step_stream<float,T=%d,PF=%d>" % (tsteps, pf)
     main_rl["launch_us"] = round(launch_ms * 1e3, 3)
     main_rl["other_bound"] = other_rl
