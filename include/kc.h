@@ -136,7 +136,9 @@ int kc_get_tuning(const kc_ctx *ctx, int32_t *tsteps, int32_t *rows, int32_t *pr
 /* Pick the fused-kernel configuration (as kc_set_tuning) by timing candidate
  * launches on the context's own fields: each launch reads the current level
  * and writes the scratch level, so the state is unchanged.  effort 0 tries 16
- * candidates, 1 the full grid of 120.  With use_cache != 0 a matching entry
+ * candidates, 1 the full grid of 120; both add, per depth and prefetch, the
+ * rows per strip that fill 1..8 whole rounds of the wavefronts the device
+ * holds at once.  With use_cache != 0 a matching entry
  * of the file named by the environment variable KC_AUTOTUNE_CACHE (one JSON
  * object per line, keyed by device, grid, precision and law) is used instead
  * of timing, and a new result is appended to it.  *gcell_s (may be NULL)

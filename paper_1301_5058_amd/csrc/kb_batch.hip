@@ -90,7 +90,8 @@ __global__ __launch_bounds__(256) void batch_kernel(BatchArgs a)
             if (__hip_atomic_load(a.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
                 return;
         } else {
-            item = (unsigned long long)blockIdx.x * 4 + (threadIdx.x >> 6);
+            item = (unsigned long long)__builtin_amdgcn_readfirstlane(blockIdx.x * 4 +
+                                                                      (threadIdx.x >> 6));
             if (item >= (unsigned long long)a.S)
                 return;
             item += (unsigned long long)a.tau0 * a.S;
@@ -146,10 +147,21 @@ __global__ __launch_bounds__(256) void batch_kernel(BatchArgs a)
         sa.cy = I.cy;
         const bool diag = ((tau + 1) % a.seb) == 0;
         DiagAcc acc{0.0, 0.0, -1.0, 0.0};
-        if (diag)
-            stream_strip<float, T, LAW, PF, true>(sa, j % I.nsx, j / I.nsx, acc);
-        else
-            stream_strip<float, T, LAW, PF, false>(sa, j % I.nsx, j / I.nsx, acc);
+        {
+            const int sx = j % I.nsx, sy = j / I.nsx;
+            const bool in = strip_interior<float, T>(sa, sx, sy);
+            if (diag) {
+                if (in)
+                    stream_strip<float, T, LAW, PF, true, false>(sa, sx, sy, acc);
+                else
+                    stream_strip<float, T, LAW, PF, true, true>(sa, sx, sy, acc);
+            } else {
+                if (in)
+                    stream_strip<float, T, LAW, PF, false, false>(sa, sx, sy, acc);
+                else
+                    stream_strip<float, T, LAW, PF, false, true>(sa, sx, sy, acc);
+            }
+        }
 
         if (diag) {
             const double sb = wave_sum64(acc.sb), sn = wave_sum64(acc.sn), m2 = wave_max64(acc.m2);
@@ -860,7 +872,8 @@ int kb_autotune(kb_batch *b, int32_t effort, int32_t sample_every)
             return bfail(b, KC_ESTATE, "instance %d has no fields", k);
     kc::Tuning cand[256];
     int n = 0;
-    kc::tuning_candidates(effort, 8, cand, &n, 256);
+    // many instances share the device, so rows are not fitted to one grid here
+    kc::tuning_candidates(effort, 8, 0, b->law, 0, 0, cand, &n, 256);
     // distinct shapes and the instances that use them
     std::vector<std::pair<int, int>> shapes;
     std::vector<int> shape_of(b->count), rep;

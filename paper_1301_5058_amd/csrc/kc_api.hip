@@ -86,9 +86,18 @@ int check_params(const kc_params *p)
 
 // Default wavefront-strip height: about 3000 strips (1.5 rounds of the 2048
 // wavefronts resident at two per SIMD), at least 8 and at most 96 rows.
-int default_rows(int precision, int tsteps, int nx, int ny)
+int default_rows(int precision, int chi_law, const kc::Tuning &t, int nx, int ny)
 {
-    const kc::StreamGeom g = kc::stream_geom(precision, tsteps, nx, ny, 1);
+    // the fewest whole rounds of the wavefronts the device holds at once with
+    // strips of at most 128 rows (no half-empty last round; long strips
+    // amortise the T-row warm-up at either end)
+    const int w = kc::resident_waves(precision, chi_law, t.tsteps, t.prefetch);
+    for (int q = 1; q <= 64 && w > 0; ++q) {
+        const int r = kc::round_fitted_rows(precision, t.tsteps, nx, ny, w, q);
+        if (r > 0 && r <= 128)
+            return r < 8 ? 8 : r;
+    }
+    const kc::StreamGeom g = kc::stream_geom(precision, t.tsteps, nx, ny, 1);
     long rows = ((long)ny * g.nsx + 2999) / 3000;
     if (rows < 8)
         rows = 8;
@@ -178,13 +187,13 @@ template <typename R> int autotune_impl(kc_ctx *c, int effort, double *best_out)
     const Fields<R> f = make_fields<R>(c); // current level in, scratch level out
     kc::Tuning cand[256];
     int n = 0;
-    kc::tuning_candidates(effort, 8, cand, &n, 256);
+    kc::tuning_candidates(effort, 8, c->p.precision, c->p.chi_law, c->nx, c->ny, cand, &n, 256);
     const double cells = (double)c->nx * c->ny;
     double best = 1e300;
     kc::Tuning bt = c->tune;
     for (int i = 0; i < n; ++i) {
-        int reps = (int)(4e8 / (cells * cand[i].tsteps));
-        reps = reps < 2 ? 2 : reps > 20 ? 20 : reps;
+        int reps = (int)(2e9 / (cells * cand[i].tsteps)); // about 2e9 cell-updates
+        reps = reps < 3 ? 3 : reps > 30 ? 30 : reps;
         double ms = 0;
         hipError_t e = kc::time_stream<R>(f, k, c->p.chi_law, cand[i], c->stream, reps, &ms);
         if (e != hipSuccess)
@@ -285,9 +294,10 @@ int kc_create(const kc_grid *g, double h, double dt, const kc_params *p, void *h
     c->esz = p->precision == KC_FP32 ? 4 : 8;
     c->stream = (hipStream_t)hip_stream;
     c->steps = p->step0;
-    c->tune.tsteps = 3; // fastest depth on gfx950 in both precisions (autotuner can change it)
+    // deepest block without register spills on gfx950 (the autotuner can change it)
+    c->tune.tsteps = 4;
     c->tune.prefetch = 4;
-    c->tune.rows = default_rows(p->precision, c->tune.tsteps, c->nx, c->ny);
+    c->tune.rows = default_rows(p->precision, p->chi_law, c->tune, c->nx, c->ny);
 
     int rc = KC_OK;
     hipError_t e = hipGetDevice(&c->device);

@@ -50,9 +50,18 @@ template <typename R>
 hipError_t time_stream(const Fields<R> &f, const Coef<R> &c, int chi_law, const Tuning &t,
                        hipStream_t s, int reps, double *ms);
 
+// Wavefronts of the fused kernel (precision, law, depth, prefetch) that the
+// device holds at once: blocks per compute unit x 4 x compute units (0 on error).
+int resident_waves(int precision, int chi_law, int tsteps, int prefetch);
+// Rows per strip such that the strips fill at most `rounds` rounds of `waves`
+// resident wavefronts (0 when no such choice exists).
+int round_fitted_rows(int precision, int tsteps, int nx, int ny, int waves, int rounds);
+
 // Candidate configurations of the autotuner: effort 0 is a short list, 1 the
-// full grid (tsteps in {1,2,3,4,6,8}, rows in 8..256, prefetch 2 or 4).
-void tuning_candidates(int effort, int max_tsteps, Tuning *out, int *n, int cap);
+// full grid (tsteps in {1,2,3,4,6,8}, rows in 8..256, prefetch 2 or 4); both
+// add, per depth, the rows that fill 1..8 whole rounds of resident wavefronts.
+void tuning_candidates(int effort, int max_tsteps, int precision, int chi_law, int nx, int ny,
+                       Tuning *out, int *n, int cap);
 
 // Autotune cache: one JSON object per line, keyed by device, grid, precision
 // and sensitivity law.  Path from KC_AUTOTUNE_CACHE, else none.

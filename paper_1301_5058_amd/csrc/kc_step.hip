@@ -73,7 +73,9 @@ template <typename R, int T, int LAW, int PF>
 __global__ __launch_bounds__(256) void step_stream(StepArgs<R> a)
 {
     const int lb = xcd_block(a.nblocks_padded);
-    const int strip = lb * 4 + (int)(threadIdx.x >> 6);
+    // wave-uniform by construction; readfirstlane lets the compiler keep the strip
+    // geometry and every row test in scalar registers
+    const int strip = __builtin_amdgcn_readfirstlane(lb * 4 + (int)(threadIdx.x >> 6));
     if (strip >= a.nstrips)
         return; // whole wavefront leaves together
     StripArgs<R> sa;
@@ -89,7 +91,11 @@ __global__ __launch_bounds__(256) void step_stream(StepArgs<R> a)
     sa.c = a.c;
     sa.b_thr = sa.cx = sa.cy = 0.0;
     DiagAcc acc{0.0, 0.0, -1.0, 0.0};
-    stream_strip<R, T, LAW, PF, false>(sa, strip % a.nsx, strip / a.nsx, acc);
+    const int sx = strip % a.nsx, sy = strip / a.nsx;
+    if (strip_interior<R, T>(sa, sx, sy))
+        stream_strip<R, T, LAW, PF, false, false>(sa, sx, sy, acc);
+    else
+        stream_strip<R, T, LAW, PF, false, true>(sa, sx, sy, acc);
 }
 
 // ---------------------------------------------------------------------------
@@ -222,7 +228,57 @@ hipError_t time_stream(const Fields<R> &f, const Coef<R> &c, int chi_law, const 
     return e;
 }
 
-void tuning_candidates(int effort, int max_tsteps, Tuning *out, int *n, int cap)
+template <typename R, int T, int LAW, int PF> static int blocks_per_cu()
+{
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, step_stream<R, T, LAW, PF>, 256, 0) !=
+        hipSuccess)
+        return 0;
+    return nb;
+}
+
+template <typename R, int LAW> static int blocks_per_cu_t(int T, int pf)
+{
+    switch (T) {
+    case 1: return pf == 4 ? blocks_per_cu<R, 1, LAW, 4>() : blocks_per_cu<R, 1, LAW, 2>();
+    case 2: return pf == 4 ? blocks_per_cu<R, 2, LAW, 4>() : blocks_per_cu<R, 2, LAW, 2>();
+    case 3: return pf == 4 ? blocks_per_cu<R, 3, LAW, 4>() : blocks_per_cu<R, 3, LAW, 2>();
+    case 4: return pf == 4 ? blocks_per_cu<R, 4, LAW, 4>() : blocks_per_cu<R, 4, LAW, 2>();
+    case 6: return pf == 4 ? blocks_per_cu<R, 6, LAW, 4>() : blocks_per_cu<R, 6, LAW, 2>();
+    case 8: return pf == 4 ? blocks_per_cu<R, 8, LAW, 4>() : blocks_per_cu<R, 8, LAW, 2>();
+    default: return 0;
+    }
+}
+
+int resident_waves(int precision, int chi_law, int tsteps, int prefetch)
+{
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return 0;
+    int nb;
+    if (precision == 0)
+        nb = chi_law == 0 ? blocks_per_cu_t<float, 0>(tsteps, prefetch)
+                          : blocks_per_cu_t<float, 1>(tsteps, prefetch);
+    else
+        nb = chi_law == 0 ? blocks_per_cu_t<double, 0>(tsteps, prefetch)
+                          : blocks_per_cu_t<double, 1>(tsteps, prefetch);
+    return nb * 4 * cus;
+}
+
+int round_fitted_rows(int precision, int tsteps, int nx, int ny, int waves, int rounds)
+{
+    if (waves <= 0 || rounds <= 0 || nx <= 0 || ny <= 0)
+        return 0;
+    const StreamGeom g = stream_geom(precision, tsteps, nx, ny, 1);
+    const long m = (long)waves * rounds / g.nsx; // strip rows that fill `rounds` rounds
+    if (m <= 0)
+        return 0;
+    return (int)((ny + m - 1) / m);
+}
+
+void tuning_candidates(int effort, int max_tsteps, int precision, int chi_law, int nx, int ny,
+                       Tuning *out, int *n, int cap)
 {
     static const int quick_t[] = {1, 2, 3, 4};
     static const int quick_r[] = {16, 32, 64, 128};
@@ -232,18 +288,34 @@ void tuning_candidates(int effort, int max_tsteps, Tuning *out, int *n, int cap)
     const int *rs = effort ? full_r : quick_r;
     const int nt = effort ? 6 : 4, nr = effort ? 10 : 4;
     int k = 0;
+    auto add = [&](int t, int r, int p) {
+        for (int i = 0; i < k && i < cap; ++i)
+            if (out[i].tsteps == t && out[i].rows == r && out[i].prefetch == p)
+                return;
+        if (k < cap) {
+            out[k].tsteps = t;
+            out[k].rows = r;
+            out[k].prefetch = p;
+        }
+        ++k;
+    };
     for (int i = 0; i < nt; ++i) {
         if (ts[i] > max_tsteps)
             continue;
-        for (int j = 0; j < nr; ++j)
-            for (int p = 0; p < (effort ? 2 : 1); ++p) {
-                if (k < cap) {
-                    out[k].tsteps = ts[i];
-                    out[k].rows = rs[j];
-                    out[k].prefetch = p ? 2 : 4;
-                }
-                ++k;
+        for (int p = 0; p < (effort ? 2 : 1); ++p) {
+            const int pf = p ? 2 : 4;
+            for (int j = 0; j < nr; ++j)
+                add(ts[i], rs[j], pf);
+            // rows that fill a whole number of rounds of resident wavefronts
+            if (nx <= 0 || ny <= 0)
+                continue;
+            const int w = resident_waves(precision, chi_law, ts[i], pf);
+            for (int q = 1; q <= 8; ++q) {
+                const int r = round_fitted_rows(precision, ts[i], nx, ny, w, q);
+                if (r >= 4 && r <= 512)
+                    add(ts[i], r, pf);
             }
+        }
     }
     *n = k < cap ? k : cap;
 }

@@ -11,6 +11,13 @@
 // launch: read b, n, sigma once, write b', n' once, plus halo re-reads that
 // mostly hit L2.
 //
+// Level L (0-based) computes only the centre rows [y0 - T + L, y1 + T - 1 - L):
+// the rows that the T-th level's output rows [y0, y1) depend on, plus one lead-in
+// row whose only purpose is the face flux below the first needed row.  The test
+// is wave-uniform, so skipped rows cost a scalar branch.  A strip whose halo
+// window lies strictly inside the domain (CHECK = false) needs no boundary-face
+// masks and no load predicates; edge strips run the checked code.
+//
 // With DIAG set, the cells a strip stores are also folded into a per-lane
 // accumulator (sum b, sum n in double, largest squared distance from the
 // envelope centre of a cell with b >= b_thr, count of such cells), in a fixed
@@ -48,7 +55,20 @@ struct DiagAcc {
     double sb, sn, m2, cnt;
 };
 
-template <typename R, int T, int LAW, int PF, bool DIAG>
+// True when every face and load of strip (sx, sy) lies inside the domain.
+template <typename R, int T>
+__device__ __forceinline__ bool strip_interior(const StripArgs<R> &a, int sx, int sy)
+{
+    constexpr int VEC = StreamShape<R>::VEC;
+    constexpr int HX = Halo<T, VEC>::HX;
+    constexpr int OW = Halo<T, VEC>::OW;
+    constexpr int WC = Halo<T, VEC>::WC;
+    const int xl = sx * OW - HX;
+    const int y0 = sy * a.rows, y1 = min(y0 + a.rows, a.ny);
+    return xl >= 0 && xl + WC <= a.nx - 1 && y0 >= T && y1 + T <= a.ny;
+}
+
+template <typename R, int T, int LAW, int PF, bool DIAG, bool CHECK>
 __device__ __forceinline__ void stream_strip(const StripArgs<R> &a, int sx, int sy, DiagAcc &acc)
 {
     constexpr int VEC = StreamShape<R>::VEC;
@@ -63,12 +83,12 @@ __device__ __forceinline__ void stream_strip(const StripArgs<R> &a, int sx, int 
     const int y1 = min(y0 + a.rows, a.ny);
     const int rs = max(y0 - T, 0); // first input row
     const int re = y1 + T;         // one past the last input row needed
-    const bool lane_in = (x0 >= 0) && (x0 < a.pitch);
+    const bool lane_in = !CHECK || ((x0 >= 0) && (x0 < a.pitch));
     const bool lane_out = (lane * VEC >= HX) && (lane * VEC < WC - HX) && (x0 < a.nx);
     bool ve[VEC]; // east face of cell k is interior
 #pragma unroll
     for (int k = 0; k < VEC; ++k)
-        ve[k] = (x0 + k >= 0) && (x0 + k + 1 < a.nx);
+        ve[k] = !CHECK || ((x0 + k >= 0) && (x0 + k + 1 < a.nx));
 
     // level state: centre row of level L and the face inflow G(S,P) below it
     R cb[T][VEC], cn[T][VEC], cD[T][VEC], cX[T][VEC], cs[T][VEC], fb[T][VEC], fn[T][VEC];
@@ -84,7 +104,7 @@ __device__ __forceinline__ void stream_strip(const StripArgs<R> &a, int sx, int 
 #pragma unroll
     for (int u = 0; u < PF; ++u) {
         const int row = rs + u;
-        if (row < a.ny && lane_in) {
+        if ((!CHECK || row < a.ny) && lane_in) {
             const size_t p = (size_t)row * a.pitch + x0;
             pb[u] = *reinterpret_cast<const vec_t *>(a.b_in + p);
             pn[u] = *reinterpret_cast<const vec_t *>(a.n_in + p);
@@ -108,7 +128,7 @@ __device__ __forceinline__ void stream_strip(const StripArgs<R> &a, int sx, int 
             }
             {
                 const int nrow = row + PF;
-                if (nrow < re && nrow < a.ny && lane_in) {
+                if (nrow < re && (!CHECK || nrow < a.ny) && lane_in) {
                     const size_t p = (size_t)nrow * a.pitch + x0;
                     pb[u] = *reinterpret_cast<const vec_t *>(a.b_in + p);
                     pn[u] = *reinterpret_cast<const vec_t *>(a.n_in + p);
@@ -124,7 +144,19 @@ __device__ __forceinline__ void stream_strip(const StripArgs<R> &a, int sx, int 
 #pragma unroll
             for (int L = 0; L < T; ++L) {
                 const int y = row - L - 1; // centre row of this level
-                const bool vv = (y >= 0) && (y + 1 < a.ny);
+                if (y < y0 - T + L || y >= y1 + T - 1 - L) {
+                    // outside this level's rows: only move the incoming row in
+#pragma unroll
+                    for (int k = 0; k < VEC; ++k) {
+                        cb[L][k] = ib[k];
+                        cn[L][k] = in[k];
+                        cD[L][k] = iD[k];
+                        cX[L][k] = iX[k];
+                        cs[L][k] = is[k];
+                    }
+                    continue;
+                }
+                const bool vv = !CHECK || ((y >= 0) && (y + 1 < a.ny));
                 R gvb[VEC], gvn[VEC], geb[VEC], gen[VEC];
 #pragma unroll
                 for (int k = 0; k < VEC; ++k)
