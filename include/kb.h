@@ -2,7 +2,7 @@
  * kb.h -- batched parameter sweeps of the chemotaxis system (see kc.h for the
  * equations and the discretisation): many independent instances, each with
  * its own grid, time step, rates, chemotactic strength and agar field, advanced
- * together by one persistent kernel launch per kb_run call.
+ * together by one kernel launch per time block of T steps.
  *
  * The paper varies the initial nutrient n0, the chemotactic strength chi0 and
  * the agar field (Sec. 3, table tabresparam) and compares the growth velocity
@@ -17,14 +17,19 @@
  * KC_MEM_DEVICE), the batch keeps padded copies in one device arena, and all
  * work is enqueued on the stream given at creation.  Status codes are kc.h's.
  *
- * Persistent launch.  kb_run issues one kernel whose workgroups pull work
- * items (time block, instance, strip) from a global counter in time-block
- * order; an item of block tau waits until every strip of block tau-1 of the
- * same instance has been stored (per-instance completion counters with
- * device-scope release / acquire).  Every item waited on was handed out
- * earlier, to a running workgroup, so the launch always drains.  Each wait is
+ * Launches.  By default kb_run issues one launch per time block (T steps of
+ * every instance); the kernel boundary orders block tau after block tau-1.
+ * The optional persistent mode (kb_set_tuning) issues one launch whose
+ * wavefronts pull work items (time block, instance, strip) from a global
+ * counter in time-block order; an item of block tau waits until the strips of
+ * block tau-1 whose output meets its halo window have published their progress
+ * flags (device-scope release / acquire).  Every item waited on was handed out
+ * earlier, to a running wavefront, so the launch always drains.  Each wait is
  * also bounded (kb_set_spin_limit): a wait that exceeds the bound stops the
- * launch and kb_run reports KC_EHIP.
+ * launch and kb_run reports KC_EHIP.  On gfx950 a device-scope release or
+ * acquire writes back or invalidates the issuing XCD's L2, once per item, so
+ * the persistent mode is slower than per-block launches at every batch size
+ * measured; the autotuner always selects per-block launches.
  */
 #ifndef KB_H
 #define KB_H
@@ -61,9 +66,10 @@ int kb_set_fields(kb_batch *bt, int32_t k, const float *b0, const float *n0, con
 
 /* Advance every instance by nsteps (a multiple of sample_every >= 1) and
  * record {t, mass, nutrient, envelope_radius, area_radius} (as
- * kc_diagnostics_device) of every instance after each sample_every steps.  One persistent launch (or, with persistent = 0 in
- * kb_set_tuning, one launch per time block).  Enqueued; fails with
- * KC_EINVAL when the samples would exceed max_samples. */
+ * kc_diagnostics_device) of every instance after each sample_every steps.
+ * Per-block launches are enqueued; the persistent mode reads its stop flag
+ * back and so synchronises the stream.  Fails with KC_EINVAL when the samples
+ * would exceed max_samples. */
 int kb_run(kb_batch *bt, int64_t nsteps, int32_t sample_every);
 
 /* Copy the samples out: out is [count][max_samples][5] doubles (unused
@@ -87,8 +93,8 @@ int kb_fit_velocity(kb_batch *bt, int32_t radius, const double *r_lo, const doub
 /* Kernel configuration.  tsteps: steps per time block (a compiled depth that
  * divides sample_every is used); rows: output rows per strip for each
  * instance (count entries, or NULL to keep); prefetch 2 or 4 (0 keeps);
- * persistent: 1 = one launch per kb_run, 0 = one launch per time block,
- * -1 keeps.  Fields, sample times and radii are bitwise independent of all
+ * persistent: 1 = one launch per kb_run, 0 = one launch per time block
+ * (the default), -1 keeps.  Fields, sample times and radii are bitwise independent of all
  * of these; the double-precision mass and nutrient sums are folded per strip,
  * so a different strip partition changes them at the level of rounding. */
 int kb_set_tuning(kb_batch *bt, int32_t tsteps, const int32_t *rows, int32_t prefetch,
@@ -97,12 +103,12 @@ int kb_get_tuning(const kb_batch *bt, int32_t *tsteps, int32_t *rows, int32_t *p
                   int32_t *persistent);
 
 /* Pick the time-block depth (a compiled depth dividing sample_every), the
- * prefetch depth and every instance's strip height by timing fused
- * single-instance launches on one instance of each distinct grid shape
- * (current level in, scratch level out: the state is unchanged), then taking
- * the depth and prefetch with the least total estimated time over all
- * instances.  effort as kc_autotune.  Requires fields on every instance.
- * Synchronous. */
+ * prefetch depth and one strip height for all instances (clamped to each
+ * grid) by timing per-block launches of the whole batch (current level in,
+ * scratch level out: the state is unchanged), and select per-block launches.
+ * effort 0 tries depths {2, 3, 4} x heights {16, 32, 64, 128, 256} with
+ * prefetch 4; effort 1 depths {1, 2, 3, 4, 6, 8} x ten heights from 8 to 256 x
+ * prefetch {2, 4}.  Requires fields on every instance.  Synchronous. */
 int kb_autotune(kb_batch *bt, int32_t effort, int32_t sample_every);
 
 /* Bound of each wait of the persistent kernel, in polls (default 2^23, a few

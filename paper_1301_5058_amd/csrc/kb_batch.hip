@@ -12,10 +12,10 @@
 //                    flag >= tau; it then publishes tau+1 for itself (release
 //                    fence, then a device-scope atomic store).
 //   PERSIST = false: one launch per time block, item = wavefront index.
-// On a sampling block each strip also folds the cells it stores into double
-// partials; the last strip of the instance to arrive (arrive[k] counter) sums
-// the partials in strip order and writes {t, mass, nutrient, envelope radius,
-// area radius}.
+// On a sampling block each strip then reads back the cells it stored
+// (strip_diag) and folds them into double partials; the last strip of the
+// instance to arrive (arrive[k] counter) sums the partials in strip order and
+// writes {t, mass, nutrient, envelope radius, area radius}.
 // kb_fit: least-squares slope of each instance's R(t) over a radius window.
 #include <math.h>
 #include <stdarg.h>
@@ -149,18 +149,12 @@ __global__ __launch_bounds__(256) void batch_kernel(BatchArgs a)
         DiagAcc acc{0.0, 0.0, -1.0, 0.0};
         {
             const int sx = j % I.nsx, sy = j / I.nsx;
-            const bool in = strip_interior<float, T>(sa, sx, sy);
-            if (diag) {
-                if (in)
-                    stream_strip<float, T, LAW, PF, true, false>(sa, sx, sy, acc);
-                else
-                    stream_strip<float, T, LAW, PF, true, true>(sa, sx, sy, acc);
-            } else {
-                if (in)
-                    stream_strip<float, T, LAW, PF, false, false>(sa, sx, sy, acc);
-                else
-                    stream_strip<float, T, LAW, PF, false, true>(sa, sx, sy, acc);
-            }
+            if (strip_interior<float, T>(sa, sx, sy))
+                stream_strip<float, T, LAW, PF, false>(sa, sx, sy);
+            else
+                stream_strip<float, T, LAW, PF, true>(sa, sx, sy);
+            if (diag)
+                strip_diag<float, T>(sa, sx, sy, acc);
         }
 
         if (diag) {
@@ -315,7 +309,7 @@ struct kb_batch {
     size_t hpin_n = 0;
     int cur = 0, nsamp = 0;
     int64_t steps = 0;
-    int T = 2, pf = 4, persistent = 1;
+    int T = 4, pf = 4, persistent = 0;
     long long spin_limit = 1ll << 23;
     int S = 0, geom_T = -1;
     bool geom_dirty = true;
@@ -358,11 +352,17 @@ bool inst_ok(const kb_instance &I)
            nn(I.kappa) && nn(I.chi) && !isnan(I.b_thr);
 }
 
-int default_rows_for(int nx, int ny)
+int default_rows_for(const kb_instance *inst, int count, int k)
 {
-    // short strips for small grids keep the item count per instance balanced
-    const int side = nx > ny ? nx : ny;
-    return side <= 256 ? 16 : side <= 512 ? 32 : 64;
+    // one strip height for the whole batch: as tall as possible (less halo
+    // work) while a time block still has about 4096 strips to spread over the
+    // device, between 8 and 128 rows, at most the instance's height
+    double cells = 0;
+    for (int i = 0; i < count; ++i)
+        cells += (double)inst[i].nx * inst[i].ny;
+    int r = (int)(cells / (248.0 * 4096.0));
+    r = r < 8 ? 8 : r > 128 ? 128 : r;
+    return r < inst[k].ny ? r : inst[k].ny;
 }
 
 // depth used for a run: a compiled depth <= tuned T that divides sample_every
@@ -580,7 +580,7 @@ int kb_create(int32_t count, const kb_instance *inst, int32_t chi_law, int32_t m
             H.cx = isnan(I.cx) ? 0.5 * (I.nx - 1) : I.cx;
             H.cy = isnan(I.cy) ? 0.5 * (I.ny - 1) : I.cy;
             H.pad_ = 0;
-            b->rows[k] = default_rows_for(I.nx, I.ny);
+            b->rows[k] = default_rows_for(inst, count, k);
         }
         hipLaunchKernelGGL(kc::series_zero, dim3(256), dim3(256), 0, b->stream, b->dseries,
                            (size_t)count * max_samples * 5);
@@ -731,14 +731,17 @@ int kb_run(kb_batch *b, int64_t nsteps, int32_t sample_every)
             KB_HIP(b, dispatch(b->law, b->pf, false, T, a, grid, b->stream));
         }
     }
-    // abort flag back to the host (small, synchronous): a stopped launch is an error
-    unsigned abort_h = 0;
-    KB_HIP(b, hipMemcpyAsync(&abort_h, a.abort_flag, sizeof(unsigned), hipMemcpyDeviceToHost,
-                             b->stream));
-    KB_HIP(b, hipStreamSynchronize(b->stream));
-    if (abort_h)
-        return bfail(b, KC_EHIP, "persistent batch launch stopped: a wait exceeded %lld polls",
-                     b->spin_limit);
+    if (b->persistent) {
+        // abort flag back to the host (small, synchronous): a stopped launch is an error
+        unsigned abort_h = 0;
+        KB_HIP(b, hipMemcpyAsync(&abort_h, a.abort_flag, sizeof(unsigned),
+                                 hipMemcpyDeviceToHost, b->stream));
+        KB_HIP(b, hipStreamSynchronize(b->stream));
+        if (abort_h)
+            return bfail(b, KC_EHIP,
+                         "persistent batch launch stopped: a wait exceeded %lld polls",
+                         b->spin_limit);
+    }
     b->cur = (int)((b->cur + blocks) & 1);
     b->steps += nsteps;
     b->nsamp += (int)ns;
@@ -870,84 +873,104 @@ int kb_autotune(kb_batch *b, int32_t effort, int32_t sample_every)
     for (int k = 0; k < b->count; ++k)
         if (!b->has_fields[k])
             return bfail(b, KC_ESTATE, "instance %d has no fields", k);
-    kc::Tuning cand[256];
-    int n = 0;
-    // many instances share the device, so rows are not fitted to one grid here
-    kc::tuning_candidates(effort, 8, 0, b->law, 0, 0, cand, &n, 256);
-    // distinct shapes and the instances that use them
-    std::vector<std::pair<int, int>> shapes;
-    std::vector<int> shape_of(b->count), rep;
-    for (int k = 0; k < b->count; ++k) {
-        const std::pair<int, int> sh(b->inst[k].nx, b->inst[k].ny);
-        int idx = -1;
-        for (size_t i = 0; i < shapes.size(); ++i)
-            if (shapes[i] == sh)
-                idx = (int)i;
-        if (idx < 0) {
-            idx = (int)shapes.size();
-            shapes.push_back(sh);
-            rep.push_back(k);
-        }
-        shape_of[k] = idx;
-    }
-    // per shape, per (T, prefetch): best rows and its time per step
-    const int depths[] = {1, 2, 3, 4, 6, 8};
-    const int nd = 6;
-    std::vector<double> best_ms(shapes.size() * nd * 2, 1e300);
-    std::vector<int> best_rows(shapes.size() * nd * 2, 32);
-    for (size_t si = 0; si < shapes.size(); ++si) {
-        const BInst &H = b->hinst[rep[si]];
-        kc::Fields<float> f;
-        f.b_in = H.b[b->cur];
-        f.n_in = H.n[b->cur];
-        f.sg = H.sg;
-        f.b_out = H.b[b->cur ^ 1];
-        f.n_out = H.n[b->cur ^ 1];
-        f.nx = H.nx;
-        f.ny = H.ny;
-        f.pitch = H.pitch;
-        const double cells = (double)H.nx * H.ny;
-        for (int i = 0; i < n; ++i) {
-            if (sample_every % cand[i].tsteps != 0)
-                continue;
-            int reps = (int)(2e8 / (cells * cand[i].tsteps));
-            reps = reps < 2 ? 2 : reps > 20 ? 20 : reps;
-            double ms = 0;
-            KB_HIP(b, kc::time_stream<float>(f, H.c, b->law, cand[i], b->stream, reps, &ms));
-            int di = 0;
-            while (depths[di] != cand[i].tsteps)
-                ++di;
-            const size_t slot = (si * nd + di) * 2 + (cand[i].prefetch == 4 ? 1 : 0);
-            const double per_step = ms / cand[i].tsteps;
-            if (per_step < best_ms[slot]) {
-                best_ms[slot] = per_step;
-                best_rows[slot] = cand[i].rows;
-            }
-        }
-    }
-    // count instances per shape, then the (T, prefetch) with least total time
-    std::vector<int> mult(shapes.size(), 0);
+    // candidates: depth (dividing sample_every) x prefetch x one strip height for
+    // every instance (clamped to its grid); each is timed on the batch itself
+    // with per-block launches that read the current level and write the
+    // scratch level, so the state is unchanged
+    static const int quick_t[] = {2, 3, 4}, full_t[] = {1, 2, 3, 4, 6, 8};
+    static const int quick_r[] = {16, 32, 64, 128, 256};
+    static const int full_r[] = {8, 16, 24, 32, 48, 64, 96, 128, 192, 256};
+    const int *ts = effort ? full_t : quick_t, nt = effort ? 6 : 3;
+    const int *rs = effort ? full_r : quick_r, nr = effort ? 10 : 5;
+    double cells = 0;
     for (int k = 0; k < b->count; ++k)
-        ++mult[shape_of[k]];
-    double best_total = 1e300;
-    int bdi = -1, bpf = 1;
-    for (int di = 0; di < nd; ++di)
-        for (int pf = 0; pf < 2; ++pf) {
-            double tot = 0;
-            for (size_t si = 0; si < shapes.size(); ++si)
-                tot += mult[si] * best_ms[(si * nd + di) * 2 + pf];
-            if (tot < best_total) {
-                best_total = tot;
-                bdi = di;
-                bpf = pf;
+        cells += (double)b->inst[k].nx * b->inst[k].ny;
+    const std::vector<int> saved_rows = b->rows;
+    const int saved_T = b->T, saved_pf = b->pf;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    KB_HIP(b, hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return bfail(b, KC_EHIP, "hipEventCreate failed");
+    }
+    double best = 1e300;
+    int bT = saved_T, bpf = saved_pf, brows = -1;
+    int rc = KC_OK;
+    for (int it = 0; it < nt && rc == KC_OK; ++it) {
+        const int T = ts[it];
+        if (sample_every % T != 0)
+            continue;
+        for (int ir = 0; ir < nr && rc == KC_OK; ++ir) {
+            for (int k = 0; k < b->count; ++k)
+                b->rows[k] = rs[ir] < b->inst[k].ny ? rs[ir] : b->inst[k].ny;
+            rc = layout(b, T);
+            if (rc != KC_OK)
+                break;
+            kc::BatchArgs a;
+            a.inst = b->dinst;
+            a.strip_inst = b->dstrip_inst;
+            a.S = b->S;
+            a.T = T;
+            a.total_items = b->S;
+            a.tau0 = 0;
+            a.parity0 = b->cur;
+            a.seb = 1 << 30; // no sampling block among the timed ones
+            a.sample_base = 0;
+            a.cap = b->cap;
+            a.step_base = b->steps;
+            a.flags = b->dflags;
+            a.arrive = b->dcnt;
+            a.fin = b->dcnt + b->count;
+            a.abort_flag = b->dcnt + 2 * b->count;
+            a.next = b->dnext;
+            a.partials = b->dpartials;
+            a.series = b->dseries;
+            a.spin_limit = b->spin_limit;
+            const dim3 grid((unsigned)((b->S + 3) / 4));
+            int reps = (int)(2e9 / (cells * T));
+            reps = reps < 3 ? 3 : reps > 30 ? 30 : reps;
+            for (int p = 0; p < (effort ? 2 : 1) && rc == KC_OK; ++p) {
+                const int pf = p ? 2 : 4;
+                hipError_t e = dispatch(b->law, pf, false, T, a, grid, b->stream); // warm-up
+                if (e == hipSuccess)
+                    e = hipEventRecord(e0, b->stream);
+                for (int r = 0; r < reps && e == hipSuccess; ++r)
+                    e = dispatch(b->law, pf, false, T, a, grid, b->stream);
+                if (e == hipSuccess)
+                    e = hipEventRecord(e1, b->stream);
+                if (e == hipSuccess)
+                    e = hipEventSynchronize(e1);
+                float ms = 0.f;
+                if (e == hipSuccess)
+                    e = hipEventElapsedTime(&ms, e0, e1);
+                if (e != hipSuccess) {
+                    rc = bfail(b, KC_EHIP, "autotune launch: %s", hipGetErrorString(e));
+                    break;
+                }
+                const double per_step = (double)ms / (reps * T);
+                if (per_step < best) {
+                    best = per_step;
+                    bT = T;
+                    bpf = pf;
+                    brows = rs[ir];
+                }
             }
         }
-    if (bdi < 0 || best_total >= 1e299)
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != KC_OK) {
+        b->rows = saved_rows;
+        b->geom_dirty = true;
+        return rc;
+    }
+    if (brows < 0)
         return bfail(b, KC_EINVAL, "no compiled depth divides sample_every = %d", sample_every);
-    b->T = depths[bdi];
-    b->pf = bpf ? 4 : 2;
+    b->T = bT;
+    b->pf = bpf;
     for (int k = 0; k < b->count; ++k)
-        b->rows[k] = best_rows[(shape_of[k] * nd + bdi) * 2 + bpf];
+        b->rows[k] = brows < b->inst[k].ny ? brows : b->inst[k].ny;
+    b->persistent = 0;
     b->geom_dirty = true;
     return KC_OK;
 }

@@ -8,7 +8,9 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "kc.h"
@@ -189,8 +191,10 @@ template <typename R> int autotune_impl(kc_ctx *c, int effort, double *best_out)
     int n = 0;
     kc::tuning_candidates(effort, 8, c->p.precision, c->p.chi_law, c->nx, c->ny, cand, &n, 256);
     const double cells = (double)c->nx * c->ny;
-    double best = 1e300;
-    kc::Tuning bt = c->tune;
+    // pass 1: every candidate once; pass 2: the six fastest again, twice each
+    // with longer runs, keeping each one's best (single timings are noisy)
+    std::vector<std::pair<double, int>> order;
+    order.reserve(n);
     for (int i = 0; i < n; ++i) {
         int reps = (int)(2e9 / (cells * cand[i].tsteps)); // about 2e9 cell-updates
         reps = reps < 3 ? 3 : reps > 30 ? 30 : reps;
@@ -198,12 +202,26 @@ template <typename R> int autotune_impl(kc_ctx *c, int effort, double *best_out)
         hipError_t e = kc::time_stream<R>(f, k, c->p.chi_law, cand[i], c->stream, reps, &ms);
         if (e != hipSuccess)
             return hipfail(c, e, "autotune launch");
-        const double per_step = ms / cand[i].tsteps;
-        if (per_step < best) {
-            best = per_step;
-            bt = cand[i];
-        }
+        order.push_back(std::make_pair(ms / cand[i].tsteps, i));
     }
+    std::sort(order.begin(), order.end());
+    const int top = n < 6 ? n : 6;
+    double best = 1e300;
+    kc::Tuning bt = c->tune;
+    for (int pass = 0; pass < 2; ++pass)
+        for (int j = 0; j < top; ++j) {
+            const kc::Tuning &t = cand[order[j].second];
+            int reps = (int)(6e9 / (cells * t.tsteps));
+            reps = reps < 6 ? 6 : reps > 90 ? 90 : reps;
+            double ms = 0;
+            hipError_t e = kc::time_stream<R>(f, k, c->p.chi_law, t, c->stream, reps, &ms);
+            if (e != hipSuccess)
+                return hipfail(c, e, "autotune launch");
+            if (ms / t.tsteps < best) {
+                best = ms / t.tsteps;
+                bt = t;
+            }
+        }
     c->tune = bt;
     *best_out = cells / (best * 1e-3) / 1e9;
     return KC_OK;

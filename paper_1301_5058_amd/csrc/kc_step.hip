@@ -90,12 +90,11 @@ __global__ __launch_bounds__(256) void step_stream(StepArgs<R> a)
     sa.rows = a.rows;
     sa.c = a.c;
     sa.b_thr = sa.cx = sa.cy = 0.0;
-    DiagAcc acc{0.0, 0.0, -1.0, 0.0};
     const int sx = strip % a.nsx, sy = strip / a.nsx;
     if (strip_interior<R, T>(sa, sx, sy))
-        stream_strip<R, T, LAW, PF, false, false>(sa, sx, sy, acc);
+        stream_strip<R, T, LAW, PF, false>(sa, sx, sy);
     else
-        stream_strip<R, T, LAW, PF, false, true>(sa, sx, sy, acc);
+        stream_strip<R, T, LAW, PF, true>(sa, sx, sy);
 }
 
 // ---------------------------------------------------------------------------

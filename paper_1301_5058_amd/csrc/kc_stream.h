@@ -14,14 +14,17 @@
 // Level L (0-based) computes only the centre rows [y0 - T + L, y1 + T - 1 - L):
 // the rows that the T-th level's output rows [y0, y1) depend on, plus one lead-in
 // row whose only purpose is the face flux below the first needed row.  The test
-// is wave-uniform, so skipped rows cost a scalar branch.  A strip whose halo
+// is wave-uniform, so skipped rows cost a scalar branch, and a group of PF rows
+// on which every level is active (the steady state between the first T - 1 + T
+// and the last rows) runs a straight-line body without it.  A strip whose halo
 // window lies strictly inside the domain (CHECK = false) needs no boundary-face
 // masks and no load predicates; edge strips run the checked code.
 //
-// With DIAG set, the cells a strip stores are also folded into a per-lane
-// accumulator (sum b, sum n in double, largest squared distance from the
-// envelope centre of a cell with b >= b_thr, count of such cells), in a fixed
-// order.
+// strip_diag reads back the cells a strip has just stored (each lane its own
+// addresses, so program order makes the stores visible) and folds them into a
+// per-lane accumulator: sum b, sum n in double, the largest squared distance
+// from the envelope centre of a cell with b >= b_thr, and the count of such
+// cells, rows ascending and columns ascending within a lane.
 #pragma once
 
 #include "kc_device.h"
@@ -48,7 +51,11 @@ template <typename R> struct StripArgs {
     int nx, ny, pitch;
     int rows; // output rows per strip
     Coef<R> c;
-    double b_thr, cx, cy; // envelope diagnostics (DIAG only)
+    double b_thr, cx, cy; // envelope diagnostics (strip_diag only)
+};
+
+template <bool B> struct BoolTag {
+    static constexpr bool value = B;
 };
 
 struct DiagAcc {
@@ -68,8 +75,8 @@ __device__ __forceinline__ bool strip_interior(const StripArgs<R> &a, int sx, in
     return xl >= 0 && xl + WC <= a.nx - 1 && y0 >= T && y1 + T <= a.ny;
 }
 
-template <typename R, int T, int LAW, int PF, bool DIAG, bool CHECK>
-__device__ __forceinline__ void stream_strip(const StripArgs<R> &a, int sx, int sy, DiagAcc &acc)
+template <typename R, int T, int LAW, int PF, bool CHECK>
+__device__ __forceinline__ void stream_strip(const StripArgs<R> &a, int sx, int sy)
 {
     constexpr int VEC = StreamShape<R>::VEC;
     constexpr int HX = Halo<T, VEC>::HX;
@@ -83,7 +90,6 @@ __device__ __forceinline__ void stream_strip(const StripArgs<R> &a, int sx, int 
     const int y1 = min(y0 + a.rows, a.ny);
     const int rs = max(y0 - T, 0); // first input row
     const int re = y1 + T;         // one past the last input row needed
-    const bool lane_in = !CHECK || ((x0 >= 0) && (x0 < a.pitch));
     const bool lane_out = (lane * VEC >= HX) && (lane * VEC < WC - HX) && (x0 < a.nx);
     bool ve[VEC]; // east face of cell k is interior
 #pragma unroll
@@ -98,23 +104,29 @@ __device__ __forceinline__ void stream_strip(const StripArgs<R> &a, int sx, int 
         for (int k = 0; k < VEC; ++k)
             cb[L][k] = cn[L][k] = cD[L][k] = cX[L][k] = cs[L][k] = fb[L][k] = fn[L][k] = R(0);
 
-    // prefetch ring: slot (row - rs) % PF
+    // Prefetch ring: slot (row - rs) % PF.  Loads are unconditional, from
+    // addresses clamped into the array: a row past the last input row or a
+    // column outside [0, pitch) yields some in-bounds value that only ever
+    // meets a zero (masked) face or a skipped level, never a stored cell.
+    // (A conditional load would make the compiler merge the two arms through
+    // a register copy, which waits for the load it was meant to hide.)
     vec_t pb[PF], pn[PF], ps[PF];
-    const vec_t zero = (vec_t)(R(0));
+    const int last_row = min(re, a.ny) - 1;
+    const int xc = min(max(x0, 0), a.pitch - VEC);
+    auto load_row = [&](int row, vec_t &vb, vec_t &vn, vec_t &vs) __attribute__((always_inline)) {
+        const size_t p = (size_t)min(row, last_row) * a.pitch + xc;
+        vb = *reinterpret_cast<const vec_t *>(a.b_in + p);
+        vn = *reinterpret_cast<const vec_t *>(a.n_in + p);
+        vs = *reinterpret_cast<const vec_t *>(a.sg + p);
+    };
 #pragma unroll
-    for (int u = 0; u < PF; ++u) {
-        const int row = rs + u;
-        if ((!CHECK || row < a.ny) && lane_in) {
-            const size_t p = (size_t)row * a.pitch + x0;
-            pb[u] = *reinterpret_cast<const vec_t *>(a.b_in + p);
-            pn[u] = *reinterpret_cast<const vec_t *>(a.n_in + p);
-            ps[u] = *reinterpret_cast<const vec_t *>(a.sg + p);
-        } else {
-            pb[u] = pn[u] = ps[u] = zero;
-        }
-    }
+    for (int u = 0; u < PF; ++u)
+        load_row(rs + u, pb[u], pn[u], ps[u]);
 
-    for (int r0 = rs; r0 < re; r0 += PF) {
+    // One group of PF rows.  With FULL every level is active on every row of
+    // the group (the steady state), so the body is one straight-line block.
+    auto group = [&](int r0, auto full_tag) __attribute__((always_inline)) {
+        constexpr bool FULL = decltype(full_tag)::value;
 #pragma unroll
         for (int u = 0; u < PF; ++u) {
             const int row = r0 + u;
@@ -126,17 +138,7 @@ __device__ __forceinline__ void stream_strip(const StripArgs<R> &a, int sx, int 
                 in[k] = pn[u][k];
                 is[k] = R(0.5) * ps[u][k];
             }
-            {
-                const int nrow = row + PF;
-                if (nrow < re && (!CHECK || nrow < a.ny) && lane_in) {
-                    const size_t p = (size_t)nrow * a.pitch + x0;
-                    pb[u] = *reinterpret_cast<const vec_t *>(a.b_in + p);
-                    pn[u] = *reinterpret_cast<const vec_t *>(a.n_in + p);
-                    ps[u] = *reinterpret_cast<const vec_t *>(a.sg + p);
-                } else {
-                    pb[u] = pn[u] = ps[u] = zero;
-                }
-            }
+            load_row(row + PF, pb[u], pn[u], ps[u]);
 #pragma unroll
             for (int k = 0; k < VEC; ++k)
                 coef<R, LAW>(is[k], in[k], ib[k], a.c.chi2, iD[k], iX[k]);
@@ -144,7 +146,7 @@ __device__ __forceinline__ void stream_strip(const StripArgs<R> &a, int sx, int 
 #pragma unroll
             for (int L = 0; L < T; ++L) {
                 const int y = row - L - 1; // centre row of this level
-                if (y < y0 - T + L || y >= y1 + T - 1 - L) {
+                if (!FULL && (y < y0 - T + L || y >= y1 + T - 1 - L)) {
                     // outside this level's rows: only move the incoming row in
 #pragma unroll
                     for (int k = 0; k < VEC; ++k) {
@@ -209,22 +211,56 @@ __device__ __forceinline__ void stream_strip(const StripArgs<R> &a, int sx, int 
                     const size_t p = (size_t)y * a.pitch + x0;
                     *reinterpret_cast<vec_t *>(a.b_out + p) = vb;
                     *reinterpret_cast<vec_t *>(a.n_out + p) = vn;
-                    if (DIAG) {
-                        const double dy = (double)y - a.cy;
+                }
+            }
+        }
+    };
+
+    // every level is active on rows [y0 + T - 1, re): lead-in groups, the
+    // steady state, then the tail (three loops, so that the steady loop
+    // carries its state in the same registers from one trip to the next)
+    const int full_lo = y0 + T - 1;
+    int r0 = rs;
+    for (; r0 < re && r0 < full_lo; r0 += PF)
+        group(r0, BoolTag<false>());
+    for (; r0 + PF <= re; r0 += PF)
+        group(r0, BoolTag<true>());
+    for (; r0 < re; r0 += PF)
+        group(r0, BoolTag<false>());
+}
+
+// Diagnostics of the output block of strip (sx, sy) after stream_strip<.., T, ..>
+// stored it (see the header comment).
+template <typename R, int T>
+__device__ __forceinline__ void strip_diag(const StripArgs<R> &a, int sx, int sy, DiagAcc &acc)
+{
+    constexpr int VEC = StreamShape<R>::VEC;
+    constexpr int HX = Halo<T, VEC>::HX;
+    constexpr int WC = Halo<T, VEC>::WC;
+    constexpr int OW = Halo<T, VEC>::OW;
+    typedef typename VecT<R, VEC>::type vec_t;
+    const int lane = threadIdx.x & 63;
+    const int x0 = sx * OW - HX + lane * VEC;
+    const int y0 = sy * a.rows;
+    const int y1 = min(y0 + a.rows, a.ny);
+    const bool lane_out = (lane * VEC >= HX) && (lane * VEC < WC - HX) && (x0 < a.nx);
+    if (!lane_out)
+        return;
+    for (int y = y0; y < y1; ++y) {
+        const size_t p = (size_t)y * a.pitch + x0;
+        const vec_t vb = *reinterpret_cast<const vec_t *>(a.b_out + p);
+        const vec_t vn = *reinterpret_cast<const vec_t *>(a.n_out + p);
+        const double dy = (double)y - a.cy;
 #pragma unroll
-                        for (int k = 0; k < VEC; ++k) {
-                            if (x0 + k < a.nx) {
-                                const double bv = (double)ob[k];
-                                acc.sb += bv;
-                                acc.sn += (double)on[k];
-                                if (bv >= a.b_thr) {
-                                    const double dx = (double)(x0 + k) - a.cx;
-                                    acc.m2 = fmax(acc.m2, dx * dx + dy * dy);
-                                    acc.cnt += 1.0;
-                                }
-                            }
-                        }
-                    }
+        for (int k = 0; k < VEC; ++k) {
+            if (x0 + k < a.nx) {
+                const double bv = (double)vb[k];
+                acc.sb += bv;
+                acc.sn += (double)vn[k];
+                if (bv >= a.b_thr) {
+                    const double dx = (double)(x0 + k) - a.cx;
+                    acc.m2 = fmax(acc.m2, dx * dx + dy * dy);
+                    acc.cnt += 1.0;
                 }
             }
         }

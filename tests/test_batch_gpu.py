@@ -167,7 +167,7 @@ def test_batch_autotune_keeps_results():
     B, _, _ = _setup(INSTANCES, max_samples=8)
     B.autotune(every, effort=0)
     T, rows, pf, _p = B.tuning()
-    assert every % T == 0 and np.all(rows >= 1) and pf in (2, 4)
+    assert every % T == 0 and np.all(rows >= 1) and pf in (2, 4) and _p == 0
     B.run(steps, every)
     ser = B.series()
     assert np.array_equal(ser[..., [0, 3, 4]], ref[0][..., [0, 3, 4]])
