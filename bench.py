@@ -33,9 +33,11 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, 8 TB/s
 # VALU issue rate: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (one lane-op per lane per clock)
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
-# algorithmic VALU lane-operations per cell-update (receptor law): coefficients 8,
-# two faces 2 x 9, two net fluxes 6, update 5 -- see the design doc section 6
-OPS_PER_CELL_UPDATE = 37
+# algorithmic VALU lane-operations per cell-update of an interior cell (receptor
+# law): coefficients 8 (sigma n b: 2 mul; chi-weighted b^2 term: 2 mul; (1+n)^2: add,
+# mul; reciprocal; product), two faces 2 x 7 (two differences, compare, select,
+# diffusivity sum, product, fused multiply-add), two net fluxes 2 x 3, update 5
+OPS_PER_CELL_UPDATE = 33
 BYTES_PER_CELL_LAUNCH = {"fp32": 20, "fp64": 40}  # read b, n, sigma; write b', n'
 SAMPLE_EVERY = 100
 T_START = time.perf_counter()

@@ -143,10 +143,11 @@ def design_grid(per_axis=16):
     return g
 
 
-def run_velocity_map(side=256, steps=8000, per_axis=16, held_out=64, judge_seeds=(101, 102, 103, 104),
+def run_velocity_map(side=256, steps=8000, per_axis=16, held_out=64, ref_seeds=(101, 102, 103, 104),
                      query=512, band=256, seed=7):
-    """Train the surrogate on solver velocities, judge it on held-out points
-    against the seed-averaged solver, and time a query map with fallback.
+    """Train the surrogate on solver velocities, compare it on held-out points
+    with the seed-averaged solver (the reference velocities), and time a query
+    map with fallback.
 
     Returns a dict of the measurements (all velocities by the area radius)."""
     rng = np.random.default_rng(seed)
@@ -173,27 +174,27 @@ def run_velocity_map(side=256, steps=8000, per_axis=16, held_out=64, judge_seeds
     torch.cuda.synchronize()
     out["fit"] = dict(iters=sum(i for i, _ in vm.SCHEDULE), batch="full", target="log v",
                       final_loss=loss, gpu_s=round(e0.elapsed_time(e1) / 1e3, 3))
-    # 3. held-out judge: random interior points, solver averaged over seeds
+    # 3. held-out reference: random interior points, solver averaged over seeds
     H = BOX_LO + (BOX_HI - BOX_LO) * rng.uniform(0.02, 0.98, (held_out, 3))
-    vj, _, gpu_judge = solver_velocities(H, side, steps, seeds=tuple(judge_seeds))
-    judge = np.nanmean(vj, axis=1)
-    spread = np.nanstd(vj, axis=1) / judge
+    vr, _, gpu_ref = solver_velocities(H, side, steps, seeds=tuple(ref_seeds))
+    vref = np.nanmean(vr, axis=1)
+    spread = np.nanstd(vr, axis=1) / vref
     pred = vm.S.predict(H.astype(np.float32)).astype(np.float64)
-    rel = np.abs(pred - judge) / judge
+    rel = np.abs(pred - vref) / vref
     # the closed-form bound with one fitted scale (what the method gives without the network)
     cb_tr = vm.S.cbar(X[ok].astype(np.float32)).astype(np.float64)
     scale = float(np.sum(cb_tr * v[ok]) / np.sum(cb_tr * cb_tr))
     cb_h = vm.S.cbar(H.astype(np.float32)).astype(np.float64)
-    rel_cb = np.abs(scale * cb_h - judge) / judge
-    out["held_out"] = dict(points=int(held_out), seeds=len(judge_seeds),
-                           judge_seed_spread_median=float(np.median(spread)),
+    rel_cb = np.abs(scale * cb_h - vref) / vref
+    out["held_out"] = dict(points=int(held_out), seeds=len(ref_seeds),
+                           ref_seed_spread_median=float(np.median(spread)),
                            surrogate_rel_err_median=float(np.median(rel)),
                            surrogate_rel_err_p95=float(np.quantile(rel, 0.95)),
                            surrogate_rel_err_max=float(np.max(rel)),
                            surrogate_within_2pct=float(np.mean(rel <= 0.02)),
                            scaled_cbar_rel_err_median=float(np.median(rel_cb)),
                            scaled_cbar_rel_err_p95=float(np.quantile(rel_cb, 0.95)),
-                           cbar_scale=scale, judge_gpu_s=round(gpu_judge, 3))
+                           cbar_scale=scale, ref_gpu_s=round(gpu_ref, 3))
     # 4. query map: query x query (n0, chi) at a = 0.3 inside the box, plus a band outside
     n0q, chq = np.meshgrid(np.linspace(BOX_LO[0], BOX_HI[0], query),
                            np.linspace(BOX_LO[1], BOX_HI[1], query), indexing="ij")
