@@ -7,7 +7,8 @@ links or calls anything here, and nothing here imports the product package.
 Contents
   step / run / diag   plain C loops (kc_oracle.c), driven through ctypes;
                       eqs. eqnadim / eqbadim of Sec. 2.4 with no-flux
-                      boundaries (eq. bconds), forward Euler.
+                      boundaries (eq. bconds), forward Euler or the
+                      two-stage Runge-Kutta method (Sec. 3) built from it.
   cbar, bstar         closed-form speed bound of Sec. 4.1 (eqs. c-bar-chi0,
                       c-bar-0) -- see cbar.py.
   fit_velocity        least-squares slope of an envelope-radius series.
@@ -55,6 +56,8 @@ def _load():
                                    ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                    ctypes.c_double, ctypes.c_int, dp, dp, dp, ctypes.c_long]
         lib.oracle_run.restype = ctypes.c_int
+        lib.oracle_run_rk2.argtypes = lib.oracle_run.argtypes
+        lib.oracle_run_rk2.restype = ctypes.c_int
         lib.oracle_diag.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, dp, dp,
                                     ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                     dp, dp, dp, dp]
@@ -89,13 +92,18 @@ def step(b, n, sigma, h, dt, **p):
     return bo, no
 
 
-def run(b, n, sigma, h, dt, nsteps, **p):
-    """nsteps forward-Euler steps; returns (b, n) as new float64 arrays."""
+def run(b, n, sigma, h, dt, nsteps, integrator="euler", **p):
+    """nsteps steps of forward Euler (integrator="euler") or of the two-stage
+    Runge-Kutta method of kc_oracle.c (integrator="rk2"); returns (b, n) as
+    new float64 arrays."""
     lib = _load()
     b, n, sigma = _f64(b).copy(), _f64(n).copy(), _f64(sigma)
     ny, nx = b.shape
-    rc = lib.oracle_run(nx, ny, float(h), float(dt), *_params(p),
-                        _ptr(b), _ptr(n), _ptr(sigma), int(nsteps))
+    if integrator not in ("euler", "rk2"):
+        raise ValueError("integrator must be 'euler' or 'rk2'")
+    fn = lib.oracle_run if integrator == "euler" else lib.oracle_run_rk2
+    rc = fn(nx, ny, float(h), float(dt), *_params(p),
+            _ptr(b), _ptr(n), _ptr(sigma), int(nsteps))
     if rc != 0:
         raise MemoryError("oracle_run: out of memory")
     return b, n

@@ -31,7 +31,9 @@
  *   - face chemotactic coefficient X = sigma n b^2 chihat(n) (eq. chemflux)
  *     taken from the donor cell: the bacteria move up the nutrient gradient,
  *     so across a face with n_Q > n_P the donor is P, otherwise Q.
- *   - forward Euler in time; every right-hand side uses the old level.
+ *   - forward Euler in time; every right-hand side uses the old level
+ *     (oracle_step), or the two-stage Runge-Kutta step built from it
+ *     (oracle_rk2_step).
  *
  * All arithmetic is IEEE double, written term by term in the order of the
  * equations above; the file is compiled without FMA contraction.
@@ -130,6 +132,61 @@ int oracle_run(int nx, int ny, double h, double dt,
     }
     free(b2);
     free(n2);
+    return 0;
+}
+
+/*
+ * One step of the explicit two-stage Runge-Kutta method.  The paper
+ * integrates in time with an explicit second-order Runge-Kutta scheme
+ * (Sec. 3) without naming it; the reading taken is Heun's method in its
+ * strong-stability-preserving form: with E the forward-Euler step above,
+ *
+ *   u1 = E(u),   u2 = E(u1),   u' = (u + u2) / 2,
+ *
+ * i.e. the average of u and two chained Euler steps (algebraically the usual
+ * u' = u + dt/2 (L(u) + L(u1))).  Every stage is an Euler step and u' a
+ * convex combination, so b >= 0 and the stability bound of E carry over.
+ * b1, n1, b2, n2: scratch levels (nx*ny each, not aliasing anything else).
+ */
+void oracle_rk2_step(int nx, int ny, double h, double dt,
+                     double D_n, double theta, double kappa, double chi, int chi_law,
+                     const double *b, const double *n, const double *sigma,
+                     double *b1, double *n1, double *b2, double *n2,
+                     double *b_out, double *n_out)
+{
+    oracle_step(nx, ny, h, dt, D_n, theta, kappa, chi, chi_law, b, n, sigma, b1, n1);
+    oracle_step(nx, ny, h, dt, D_n, theta, kappa, chi, chi_law, b1, n1, sigma, b2, n2);
+    const long cells = (long)nx * ny;
+#pragma omp parallel for schedule(static)
+    for (long p = 0; p < cells; ++p) {
+        b_out[p] = 0.5 * (b[p] + b2[p]);
+        n_out[p] = 0.5 * (n[p] + n2[p]);
+    }
+}
+
+/*
+ * nsteps steps of oracle_rk2_step in place on (b, n).  Returns 0, or -5 when
+ * the scratch levels cannot be allocated.
+ */
+int oracle_run_rk2(int nx, int ny, double h, double dt,
+                   double D_n, double theta, double kappa, double chi, int chi_law,
+                   double *b, double *n, const double *sigma, long nsteps)
+{
+    const size_t cells = (size_t)nx * (size_t)ny;
+    double *buf = (double *)malloc(6 * cells * sizeof(double));
+    if (!buf)
+        return -5;
+    double *b1 = buf, *n1 = buf + cells, *b2 = buf + 2 * cells, *n2 = buf + 3 * cells;
+    double *bn = buf + 4 * cells, *nn = buf + 5 * cells;
+    for (long s = 0; s < nsteps; ++s) {
+        oracle_rk2_step(nx, ny, h, dt, D_n, theta, kappa, chi, chi_law, b, n, sigma,
+                        b1, n1, b2, n2, bn, nn);
+        for (size_t p = 0; p < cells; ++p) {
+            b[p] = bn[p];
+            n[p] = nn[p];
+        }
+    }
+    free(buf);
     return 0;
 }
 

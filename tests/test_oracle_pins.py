@@ -388,3 +388,93 @@ def test_velocity_fit_recovers_slope_inside_window():
     assert v == pytest.approx(0.0123, rel=1e-12)
     assert k == int(np.sum((R >= 10) & (R <= 40)))
     assert math.isnan(oracle.fit_velocity(t, R, 1e9, 2e9)[0])
+
+
+# ----------------------------------------------------------------------------
+# The two-stage Runge-Kutta step (Sec. 3: explicit second-order Runge-Kutta)
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("nx,ny,kx,ky,h,D_n", [(32, 24, 3, 5, 0.7, 1.3), (20, 20, 4, 0, 0.5, 0.8)])
+def test_rk2_fourier_mode_amplification_is_the_second_order_polynomial(nx, ny, kx, ky, h, D_n):
+    # On a cosine mode the semi-discrete nutrient operator is the scalar
+    # z / dt, z = -4 lam D_n (sin^2 + sin^2); an explicit two-stage second
+    # order Runge-Kutta step multiplies the mode by the degree-2 Taylor
+    # polynomial of exp(z), 1 + z + z^2 / 2.
+    dt = 0.2 * h * h / D_n
+    i = np.arange(nx) + 0.5
+    j = np.arange(ny) + 0.5
+    mode = np.cos(np.pi * ky * j / ny)[:, None] * np.cos(np.pi * kx * i / nx)[None, :]
+    nbar, A = 0.9, 0.25
+    sig = 1.0 + 0.5 * np.random.default_rng(2).uniform(-1, 1, (ny, nx))
+    steps = 300
+    b, n = oracle.run(np.zeros((ny, nx)), nbar + A * mode, sig, h, dt, steps, integrator="rk2",
+                      D_n=D_n, chi=0.7)
+    z = -4.0 * dt * D_n / h ** 2 * (np.sin(np.pi * kx / (2 * nx)) ** 2 +
+                                    np.sin(np.pi * ky / (2 * ny)) ** 2)
+    g = 1.0 + z + 0.5 * z * z
+    assert np.max(np.abs(n - (nbar + A * g ** steps * mode))) <= 1e-13
+    assert np.all(b == 0.0)
+
+
+def _logistic(b0, c, t):
+    # b' = b (c - b) (uniform fields, theta = kappa = 1, n = c - b): exact solution
+    e = np.exp(c * t)
+    return c * b0 * e / (c + b0 * (e - 1.0))
+
+
+def test_rk2_uniform_fields_follow_the_logistic_law_to_second_order():
+    # Uniform fields carry no flux, and with theta = kappa = 1 the system is
+    # the logistic ODE for b with n = c - b (the kinetics of eq. goodkinetics).
+    b0, n0, T = 0.05, 0.9, 4.0
+    c = b0 + n0
+    errs = {}
+    for integ in ("euler", "rk2"):
+        e = []
+        for k in (40, 80, 160, 320):
+            dt = T / k
+            b, n = oracle.run(np.full((3, 4), b0), np.full((3, 4), n0), np.ones((3, 4)), 1.0, dt, k,
+                              integrator=integ, chi=0.3)
+            assert np.ptp(b) == 0.0 and np.ptp(n) == 0.0
+            assert abs(b[0, 0] + n[0, 0] - c) <= 1e-14
+            e.append(abs(b[0, 0] - _logistic(b0, c, T)))
+        errs[integ] = e
+    rk2 = [math.log2(errs["rk2"][i] / errs["rk2"][i + 1]) for i in range(3)]
+    eul = [math.log2(errs["euler"][i] / errs["euler"][i + 1]) for i in range(3)]
+    assert min(rk2) >= 1.95 and max(rk2) <= 2.05
+    assert min(eul) >= 0.9 and max(eul) <= 1.1
+
+
+def test_rk2_converges_at_second_order_in_time_on_smooth_fields():
+    # Smooth data on a fixed grid: the spatial operator is fixed, so halving dt
+    # shows the temporal order of the integrator alone (reference: dt / 64).
+    nx = ny = 16
+    i = (np.arange(nx) + 0.5) / nx
+    j = (np.arange(ny) + 0.5) / ny
+    X, Y = np.meshgrid(i, j)
+    b0 = 0.3 + 0.1 * np.cos(np.pi * X) * np.cos(2 * np.pi * Y)
+    n0 = 0.8 + 0.1 * np.cos(2 * np.pi * X) * np.cos(np.pi * Y)
+    sig = 1.0 + 0.2 * np.cos(np.pi * X + 0.3) * np.sin(np.pi * Y + 0.1)
+    T, base = 2.0, 0.1
+    kw = dict(chi=1.0)
+    ref = oracle.run(b0, n0, sig, 1.0, base / 64, int(round(T / (base / 64))), integrator="rk2", **kw)
+    def err(integ, dt):
+        b, n = oracle.run(b0, n0, sig, 1.0, dt, int(round(T / dt)), integrator=integ, **kw)
+        return max(np.max(np.abs(b - ref[0])), np.max(np.abs(n - ref[1])))
+    rk2 = [err("rk2", base / m) for m in (1, 2, 4)]
+    eul = [err("euler", base / m) for m in (1, 2, 4)]
+    for e in (rk2, eul):
+        assert e[0] > e[1] > e[2] > 0
+    assert math.log2(rk2[1] / rk2[2]) >= 1.9
+    assert math.log2(eul[1] / eul[2]) <= 1.1
+    assert rk2[0] < 0.2 * eul[0]
+
+
+def test_rk2_keeps_the_discrete_invariants_and_positivity():
+    b0, n0, s = _small_fields()
+    dt = workload.config_dt(b0, n0, s)
+    b, n = oracle.run(b0, n0, s, 1.0, dt, 500, integrator="rk2", theta=0.0, chi=0.5)
+    m0 = np.sum(b0.astype(np.float64))
+    assert abs(np.sum(b) - m0) / m0 <= 1e-13
+    b, n = oracle.run(b0, n0, s, 1.0, dt, 500, integrator="rk2", theta=1.0, chi=0.5)
+    tot0 = m0 + np.sum(n0.astype(np.float64))
+    assert abs(np.sum(b) + np.sum(n) - tot0) / tot0 <= 1e-13
+    assert np.min(b) >= 0.0 and np.min(n) >= 0.0
