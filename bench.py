@@ -13,8 +13,8 @@ that tracks the colony envelope does.  Inputs are resident in HBM before the
 timed region.  Prints one JSON line.
 
 The line also carries, under "extras", the other workloads of the solver:
-the FP64 variant and chi = 0 at 4096^2, the 16384^2 grid (20,000 steps), the
-256-instance batched
+the FP64 variant, chi = 0 and the two-stage Runge-Kutta integrator (FP32 and
+FP64) at 4096^2, the 16384^2 grid (20,000 steps), the 256-instance batched
 sweep (30,000 steps, one persistent launch), and the velocity map (surrogate
 with solver fallback).  --no-extras skips them.
 """
@@ -38,12 +38,16 @@ VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 # mul; reciprocal; product), two faces 2 x 7 (two differences, compare, select,
 # diffusivity sum, product, fused multiply-add), two net fluxes 2 x 3, update 5
 OPS_PER_CELL_UPDATE = 33
+# a two-stage Runge-Kutta step: two Euler stages and the average (add, multiply)
+# of b and n
+OPS_PER_RK2_UPDATE = 2 * OPS_PER_CELL_UPDATE + 4
 BYTES_PER_CELL_LAUNCH = {"fp32": 20, "fp64": 40}  # read b, n, sigma; write b', n'
 SAMPLE_EVERY = 100
 T_START = time.perf_counter()
 METRIC = "GCell-updates/s & % HBM peak (4096^2 FP32); velocity-map pts/s at <=2% err"
-STEP_SOURCES = ("paper_1301_5058_amd/csrc/kc_step.hip", "paper_1301_5058_amd/csrc/kc_stream.h",
-                "paper_1301_5058_amd/csrc/kc_device.h")
+STEP_SOURCES = ("paper_1301_5058_amd/csrc/kc_step.hip", "paper_1301_5058_amd/csrc/kc_step_kernels.h",
+                "paper_1301_5058_amd/csrc/kc_stream_f32_euler.hip",
+                "paper_1301_5058_amd/csrc/kc_stream.h", "paper_1301_5058_amd/csrc/kc_device.h")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_stream_4096_fp32_traffic.txt")
 # shipped autotune database (written by paper_1301_5058_amd/tune_db.py on an MI355X);
 # grids without an entry are timed on the spot
@@ -119,17 +123,17 @@ def launch_probe(S, stream, launches=60):
     return e0.elapsed_time(e1) / launches
 
 
-def roofline(precision, cells, tsteps, launch_ms):
+def roofline(precision, cells, tsteps, launch_ms, ops_per_update=OPS_PER_CELL_UPDATE):
     """Roofline of the fused step kernel: the bound (HBM or VALU) with the
     larger fraction of its peak is reported as the kernel's bound."""
     bytes_per = BYTES_PER_CELL_LAUNCH[precision] * cells
     gbs = bytes_per / (launch_ms / 1e3) / 1e9
-    tops = OPS_PER_CELL_UPDATE * cells * tsteps / (launch_ms / 1e3) / 1e12
+    tops = ops_per_update * cells * tsteps / (launch_ms / 1e3) / 1e12
     hbm = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
            "frac": round(gbs / HBM_PEAK_GBS, 4), "alg_bytes_per_launch": bytes_per}
     alu = {"bound": "alu", "achieved": round(tops, 3), "peak": round(VALU_PEAK_TOPS, 2),
            "unit": "Tops/s", "frac": round(tops / VALU_PEAK_TOPS, 4),
-           "alg_ops_per_launch": OPS_PER_CELL_UPDATE * cells * tsteps}
+           "alg_ops_per_launch": ops_per_update * cells * tsteps}
     return (alu, hbm) if alu["frac"] > hbm["frac"] else (hbm, alu)
 
 
@@ -238,8 +242,9 @@ def run(args):
     return out
 
 
-def single_variant(nx, n0, a, chi, precision, steps, tune_effort=0):
-    """GCell-updates/s of one single-instance configuration (autotuned)."""
+def single_variant(nx, n0, a, chi, precision, steps, tune_effort=0, integrator="euler"):
+    """GCell-updates/s of one single-instance configuration (autotuned); with
+    integrator="rk2" an update is one two-stage Runge-Kutta step."""
     import numpy as np
     import torch
     from paper_1301_5058_amd import workload
@@ -249,17 +254,20 @@ def single_variant(nx, n0, a, chi, precision, steps, tune_effort=0):
     if precision == "fp64":
         b, n, s = (x.astype(np.float64) for x in (b, n, s))
     stream = torch.cuda.current_stream()
-    S = Solver(nx, nx, dt=dt, chi=chi, precision=precision, b_thr=0.5 * n0, stream=stream)
+    S = Solver(nx, nx, dt=dt, chi=chi, precision=precision, b_thr=0.5 * n0, stream=stream,
+               integrator=integrator)
     S.set_fields(*(torch.from_numpy(x).cuda() for x in (b, n, s)))
     S.autotune(effort=tune_effort, use_cache=True)
     T, rows, pf = S.tuning()
     S.step(100)
     ms = timed_run(S, stream, steps)
     lm = launch_probe(S, stream, 20)
-    rl, _ = roofline(precision, nx * nx, T, lm)
+    ops = OPS_PER_RK2_UPDATE if integrator == "rk2" else OPS_PER_CELL_UPDATE
+    rl, _ = roofline(precision, nx * nx, T, lm, ops)
     S.close()
     return {"gcell_s": round(nx * nx * steps / (ms / 1e3) / 1e9, 2), "steps": steps,
-            "tsteps": T, "rows": rows, "prefetch": pf, "roofline_bound": rl["bound"],
+            "integrator": integrator, "tsteps": T, "rows": rows, "prefetch": pf,
+            "launch_us": round(lm * 1e3, 2), "roofline_bound": rl["bound"],
             "roofline_frac": rl["frac"]}
 
 
@@ -347,6 +355,10 @@ def extras(args):
     progress("fp64 4096^2: %s" % ex["fp64_4096"])
     ex["chi0_4096_fp32"] = single_variant(4096, 0.5, 0.5, 0.0, "fp32", 20000)
     progress("chi=0 4096^2: %s" % ex["chi0_4096_fp32"])
+    ex["rk2_4096_fp32"] = single_variant(4096, 0.5, 0.5, 1.0, "fp32", 20000, integrator="rk2")
+    progress("rk2 4096^2: %s" % ex["rk2_4096_fp32"])
+    ex["rk2_4096_fp64"] = single_variant(4096, 0.5, 0.5, 1.0, "fp64", 4000, integrator="rk2")
+    progress("rk2 fp64 4096^2: %s" % ex["rk2_4096_fp64"])
     ex["hires_16384"] = hires(20000)
     progress("16384^2: %s" % ex["hires_16384"])
     ex["sweep_256"] = sweep()

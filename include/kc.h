@@ -59,6 +59,11 @@ extern "C" {
 enum { KC_FP32 = 0, KC_FP64 = 1 };
 enum { KC_CHI_RECEPTOR = 0, KC_CHI_CONSTANT = 1 };
 enum { KC_MEM_HOST = 0, KC_MEM_DEVICE = 1 };
+/* Time integrator.  KC_EULER: forward Euler.  KC_RK2: the explicit two-stage
+ * Runge-Kutta method the paper integrates with (Sec. 3), read as Heun's method
+ * in strong-stability-preserving form: with E one forward-Euler step,
+ * u' = (u + E(E(u))) / 2.  Both have the same stability bound. */
+enum { KC_EULER = 0, KC_RK2 = 1 };
 
 typedef struct kc_ctx kc_ctx;
 
@@ -77,10 +82,12 @@ typedef struct {
     double b_thr;      /* envelope threshold: cells with b >= b_thr count for the radius   */
     double cx, cy;     /* envelope centre in cell-index units (default (nx-1)/2, (ny-1)/2) */
     int64_t step0;     /* step count at which the given fields sit (time = steps * dt)     */
+    int32_t integrator; /* KC_EULER or KC_RK2                                              */
 } kc_params;
 
 /* Fill *p with the normalised defaults: D_n = theta = kappa = 1, chi = 0,
- * receptor law, FP32, b_thr = 0.5, centre unset (NaN -> grid centre), step0 = 0. */
+ * receptor law, FP32, b_thr = 0.5, centre unset (NaN -> grid centre), step0 = 0,
+ * forward Euler. */
 void kc_default_params(kc_params *p);
 
 /* Create a context for grid g, cell width h > 0 and time step dt > 0 on the
@@ -127,7 +134,8 @@ double kc_suggest_dt(double h, double D_n, double max_sigma_n_b);
 int kc_check_fields(int32_t nx, int32_t ny, int precision, const void *b0, const void *n0,
                     const void *sigma, double *max_sigma_n_b);
 
-/* Kernel configuration: tsteps = time steps fused into one launch (1..8),
+/* Kernel configuration: tsteps = time steps fused into one launch (1..8; 1..3
+ * with KC_RK2, whose steps take two levels of the fused kernel each),
  * rows = output rows per wavefront strip (>= 1), prefetch = rows loaded ahead
  * (2 or 4).  0 keeps the current value.  Results do not depend on it. */
 int kc_set_tuning(kc_ctx *ctx, int32_t tsteps, int32_t rows, int32_t prefetch);

@@ -833,7 +833,7 @@ int kb_set_tuning(kb_batch *b, int32_t tsteps, const int32_t *rows, int32_t pref
             if (rows[k] < 1)
                 return bfail(b, KC_EINVAL, "rows[%d] < 1", k);
     if (tsteps)
-        b->T = kc::stream_depth_at_most(tsteps);
+        b->T = kc::stream_depth_at_most(tsteps, kc::INTEG_EULER);
     if (rows) {
         for (int k = 0; k < b->count; ++k)
             b->rows[k] = rows[k];

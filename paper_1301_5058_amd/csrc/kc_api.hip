@@ -28,6 +28,7 @@ struct kc_ctx {
     int device = 0;
     void *b[2] = {nullptr, nullptr};
     void *n[2] = {nullptr, nullptr};
+    void *b1 = nullptr, *n1 = nullptr; // stage-1 level of the Runge-Kutta reference path
     void *sg = nullptr;
     int cur = 0;
     bool has_fields = false;
@@ -83,23 +84,24 @@ int check_params(const kc_params *p)
         return KC_EINVAL;
     if (isnan(p->b_thr) || p->step0 < 0)
         return KC_EINVAL;
+    if (p->integrator != KC_EULER && p->integrator != KC_RK2)
+        return KC_EINVAL;
     return KC_OK;
 }
 
-// Default wavefront-strip height: about 3000 strips (1.5 rounds of the 2048
-// wavefronts resident at two per SIMD), at least 8 and at most 96 rows.
-int default_rows(int precision, int chi_law, const kc::Tuning &t, int nx, int ny)
+// Default wavefront-strip height: the fewest whole rounds of the wavefronts the
+// device holds at once with strips of at most 128 rows.
+int default_rows(int precision, int chi_law, int integrator, const kc::Tuning &t, int nx, int ny)
 {
-    // the fewest whole rounds of the wavefronts the device holds at once with
-    // strips of at most 128 rows (no half-empty last round; long strips
-    // amortise the T-row warm-up at either end)
-    const int w = kc::resident_waves(precision, chi_law, t.tsteps, t.prefetch);
+    // no half-empty last round; long strips amortise the warm-up rows at either end
+    const int w = kc::resident_waves(precision, chi_law, integrator, t.tsteps, t.prefetch);
+    const int levels = kc::stream_levels(integrator, t.tsteps);
     for (int q = 1; q <= 64 && w > 0; ++q) {
-        const int r = kc::round_fitted_rows(precision, t.tsteps, nx, ny, w, q);
+        const int r = kc::round_fitted_rows(precision, levels, nx, ny, w, q);
         if (r > 0 && r <= 128)
             return r < 8 ? 8 : r;
     }
-    const kc::StreamGeom g = kc::stream_geom(precision, t.tsteps, nx, ny, 1);
+    const kc::StreamGeom g = kc::stream_geom(precision, levels, nx, ny, 1);
     long rows = ((long)ny * g.nsx + 2999) / 3000;
     if (rows < 8)
         rows = 8;
@@ -137,18 +139,44 @@ template <typename R> Fields<R> make_fields(const kc_ctx *c)
 template <typename R> int step_impl(kc_ctx *c, int64_t nsteps)
 {
     const Coef<R> k = make_coef<R>(c);
+    const int integ = c->p.integrator;
+    if (c->ref && integ == KC_RK2 && !c->b1) {
+        // the reference Runge-Kutta path keeps its first stage in a level of its own
+        const size_t bytes = (size_t)c->pitch * c->ny * c->esz;
+        hipError_t e = hipMalloc(&c->b1, bytes);
+        if (e == hipSuccess)
+            e = hipMalloc(&c->n1, bytes);
+        if (e == hipSuccess)
+            e = hipMemset(c->b1, 0, bytes);
+        if (e == hipSuccess)
+            e = hipMemset(c->n1, 0, bytes);
+        if (e != hipSuccess)
+            return hipfail(c, e, "stage-1 level allocation");
+    }
     while (nsteps > 0) {
         const Fields<R> f = make_fields<R>(c);
         hipError_t e;
         int adv;
-        if (c->ref) {
+        if (c->ref && integ == KC_RK2) {
+            // u1 = E(u) into the stage level, then u' = (u + E(u1)) / 2
+            Fields<R> f1 = f;
+            f1.b_out = (R *)c->b1;
+            f1.n_out = (R *)c->n1;
+            e = kc::launch_ref<R>(f1, k, c->p.chi_law, c->stream);
+            Fields<R> f2 = f;
+            f2.b_in = (const R *)c->b1;
+            f2.n_in = (const R *)c->n1;
+            if (e == hipSuccess)
+                e = kc::launch_ref<R>(f2, k, c->p.chi_law, c->stream, f.b_in, f.n_in);
+            adv = 1;
+        } else if (c->ref) {
             e = kc::launch_ref<R>(f, k, c->p.chi_law, c->stream);
             adv = 1;
         } else {
             kc::Tuning t = c->tune;
             const int64_t want = nsteps < t.tsteps ? nsteps : t.tsteps;
-            t.tsteps = kc::stream_depth_at_most((int)want);
-            e = kc::launch_stream<R>(f, k, c->p.chi_law, t, c->stream);
+            t.tsteps = kc::stream_depth_at_most((int)want, integ);
+            e = kc::launch_stream<R>(f, k, c->p.chi_law, integ, t, c->stream);
             adv = t.tsteps;
         }
         if (e != hipSuccess)
@@ -189,7 +217,8 @@ template <typename R> int autotune_impl(kc_ctx *c, int effort, double *best_out)
     const Fields<R> f = make_fields<R>(c); // current level in, scratch level out
     kc::Tuning cand[256];
     int n = 0;
-    kc::tuning_candidates(effort, 8, c->p.precision, c->p.chi_law, c->nx, c->ny, cand, &n, 256);
+    kc::tuning_candidates(effort, c->p.precision, c->p.chi_law, c->p.integrator, c->nx, c->ny,
+                          cand, &n, 256);
     const double cells = (double)c->nx * c->ny;
     // pass 1: every candidate once; pass 2: the six fastest again, twice each
     // with longer runs, keeping each one's best (single timings are noisy)
@@ -199,7 +228,8 @@ template <typename R> int autotune_impl(kc_ctx *c, int effort, double *best_out)
         int reps = (int)(2e9 / (cells * cand[i].tsteps)); // about 2e9 cell-updates
         reps = reps < 3 ? 3 : reps > 30 ? 30 : reps;
         double ms = 0;
-        hipError_t e = kc::time_stream<R>(f, k, c->p.chi_law, cand[i], c->stream, reps, &ms);
+        hipError_t e =
+            kc::time_stream<R>(f, k, c->p.chi_law, c->p.integrator, cand[i], c->stream, reps, &ms);
         if (e != hipSuccess)
             return hipfail(c, e, "autotune launch");
         order.push_back(std::make_pair(ms / cand[i].tsteps, i));
@@ -214,7 +244,8 @@ template <typename R> int autotune_impl(kc_ctx *c, int effort, double *best_out)
             int reps = (int)(6e9 / (cells * t.tsteps));
             reps = reps < 6 ? 6 : reps > 90 ? 90 : reps;
             double ms = 0;
-            hipError_t e = kc::time_stream<R>(f, k, c->p.chi_law, t, c->stream, reps, &ms);
+            hipError_t e =
+                kc::time_stream<R>(f, k, c->p.chi_law, c->p.integrator, t, c->stream, reps, &ms);
             if (e != hipSuccess)
                 return hipfail(c, e, "autotune launch");
             if (ms / t.tsteps < best) {
@@ -245,6 +276,7 @@ void kc_default_params(kc_params *p)
     p->cx = NAN;
     p->cy = NAN;
     p->step0 = 0;
+    p->integrator = KC_EULER;
 }
 
 const char *kc_strerror(int s)
@@ -312,10 +344,11 @@ int kc_create(const kc_grid *g, double h, double dt, const kc_params *p, void *h
     c->esz = p->precision == KC_FP32 ? 4 : 8;
     c->stream = (hipStream_t)hip_stream;
     c->steps = p->step0;
-    // deepest block without register spills on gfx950 (the autotuner can change it)
-    c->tune.tsteps = 4;
+    // deepest block without register spills on gfx950, 4 levels (the autotuner
+    // can change it)
+    c->tune.tsteps = p->integrator == KC_RK2 ? 2 : 4;
     c->tune.prefetch = 4;
-    c->tune.rows = default_rows(p->precision, p->chi_law, c->tune, c->nx, c->ny);
+    c->tune.rows = default_rows(p->precision, p->chi_law, p->integrator, c->tune, c->nx, c->ny);
 
     int rc = KC_OK;
     hipError_t e = hipGetDevice(&c->device);
@@ -369,7 +402,7 @@ void kc_destroy(kc_ctx *c)
         return;
     if (c->stream || c->b[0])
         (void)hipStreamSynchronize(c->stream);
-    for (void *q : {c->b[0], c->n[0], c->b[1], c->n[1], c->sg})
+    for (void *q : {c->b[0], c->n[0], c->b[1], c->n[1], c->sg, c->b1, c->n1})
         if (q)
             (void)hipFree(q);
     if (c->dparts)
@@ -527,7 +560,7 @@ int kc_set_tuning(kc_ctx *c, int32_t tsteps, int32_t rows, int32_t prefetch)
     if (tsteps < 0 || tsteps > 8 || rows < 0 || (prefetch != 0 && prefetch != 2 && prefetch != 4))
         return fail(c, KC_EINVAL, "bad tuning (%d, %d, %d)", tsteps, rows, prefetch);
     if (tsteps)
-        c->tune.tsteps = kc::stream_depth_at_most(tsteps);
+        c->tune.tsteps = kc::stream_depth_at_most(tsteps, c->p.integrator);
     if (rows)
         c->tune.rows = rows;
     if (prefetch)
@@ -558,11 +591,12 @@ int kc_autotune(kc_ctx *c, int32_t effort, int32_t use_cache, double *gcell_s)
     if (!c->has_fields)
         return fail(c, KC_ESTATE, "kc_autotune before kc_set_fields");
     char key[256];
-    kc::device_key(key, sizeof key, c->nx, c->ny, c->p.precision, c->p.chi_law);
+    kc::device_key(key, sizeof key, c->nx, c->ny, c->p.precision, c->p.chi_law,
+                   c->p.integrator);
     if (gcell_s)
         *gcell_s = 0.0;
     kc::Tuning t;
-    if (use_cache && kc::cache_lookup(key, &t)) {
+    if (use_cache && kc::cache_lookup(key, c->p.integrator, &t)) {
         c->tune = t;
         return KC_OK;
     }

@@ -86,6 +86,13 @@ __device__ __forceinline__ void update(R b, R n, R Fb, R Fn, const Coef<R> &c, R
     no = fmaR(-c.upt, nb, fmaR(c.lamDn, Fn, n));
 }
 
+// Result of a step of the two-stage Runge-Kutta method (Sec. 3): the average of
+// the step's input u and the two chained Euler stages E(E(u)).
+template <typename R> __device__ __forceinline__ R rk2_average(R u, R e2)
+{
+    return R(0.5) * (u + e2);
+}
+
 // ---------------------------------------------------------------------------
 // Cross-lane moves inside a 64-lane wavefront (DPP wave shifts, GFX9 family).
 //   from_next(v): lane i receives lane i+1's v (lane 63 receives 0)

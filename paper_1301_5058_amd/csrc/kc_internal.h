@@ -21,53 +21,62 @@ template <typename R> struct Fields {
 };
 
 struct Tuning {
-    int tsteps;   // steps fused in one launch
+    int tsteps;   // time steps fused in one launch (Euler, or Runge-Kutta: 2 levels each)
     int rows;     // output rows per wavefront strip
     int prefetch; // rows loaded ahead (2 or 4)
 };
 
-// Largest fused depth with a compiled kernel that is <= t.
-int stream_depth_at_most(int t);
+// Integrators (kc.h's KC_EULER / KC_RK2).
+enum { INTEG_EULER = 0, INTEG_RK2 = 1 };
+
+// Largest fused depth (time steps) with a compiled kernel that is <= t.
+int stream_depth_at_most(int t, int integrator);
+// Levels (Euler stages) of a launch of `tsteps` steps: the halo width.
+int stream_levels(int integrator, int tsteps);
 
 // Launch geometry of the fused kernel (for the planner and the autotuner).
 struct StreamGeom {
     int nsx, nsy, nstrips, nblocks_padded, out_cols;
 };
-StreamGeom stream_geom(int precision, int tsteps, int nx, int ny, int rows);
+StreamGeom stream_geom(int precision, int levels, int nx, int ny, int rows);
 
-// One launch advancing `tsteps` steps with the fused kernel.
+// One launch advancing t.tsteps steps of `integrator` with the fused kernel.
 template <typename R>
-hipError_t launch_stream(const Fields<R> &f, const Coef<R> &c, int chi_law, const Tuning &t,
-                         hipStream_t s);
-// One launch advancing one step with the global-memory reference kernel.
+hipError_t launch_stream(const Fields<R> &f, const Coef<R> &c, int chi_law, int integrator,
+                         const Tuning &t, hipStream_t s);
+// One forward-Euler step with the global-memory reference kernel; with b_avg
+// non-null the result is averaged with (b_avg, n_avg) (Runge-Kutta stage 2).
 template <typename R>
-hipError_t launch_ref(const Fields<R> &f, const Coef<R> &c, int chi_law, hipStream_t s);
+hipError_t launch_ref(const Fields<R> &f, const Coef<R> &c, int chi_law, hipStream_t s,
+                      const R *b_avg = nullptr, const R *n_avg = nullptr);
 
 // Average duration (ms) of one fused launch with tuning t, from `reps` launches
 // after one warm-up launch, timed with HIP events on stream s.  The launch
 // reads f's input level and writes its output level; nothing else changes.
 template <typename R>
-hipError_t time_stream(const Fields<R> &f, const Coef<R> &c, int chi_law, const Tuning &t,
-                       hipStream_t s, int reps, double *ms);
+hipError_t time_stream(const Fields<R> &f, const Coef<R> &c, int chi_law, int integrator,
+                       const Tuning &t, hipStream_t s, int reps, double *ms);
 
-// Wavefronts of the fused kernel (precision, law, depth, prefetch) that the
-// device holds at once: blocks per compute unit x 4 x compute units (0 on error).
-int resident_waves(int precision, int chi_law, int tsteps, int prefetch);
-// Rows per strip such that the strips fill at most `rounds` rounds of `waves`
-// resident wavefronts (0 when no such choice exists).
-int round_fitted_rows(int precision, int tsteps, int nx, int ny, int waves, int rounds);
+// Wavefronts of the fused kernel (precision, law, integrator, depth, prefetch)
+// that the device holds at once: blocks per compute unit x 4 x compute units
+// (0 on error).
+int resident_waves(int precision, int chi_law, int integrator, int tsteps, int prefetch);
+// Rows per strip such that the strips of a launch of `levels` levels fill at
+// most `rounds` rounds of `waves` resident wavefronts (0 when none does).
+int round_fitted_rows(int precision, int levels, int nx, int ny, int waves, int rounds);
 
 // Candidate configurations of the autotuner: effort 0 is a short list, 1 the
-// full grid (tsteps in {1,2,3,4,6,8}, rows in 8..256, prefetch 2 or 4); both
-// add, per depth, the rows that fill 1..8 whole rounds of resident wavefronts.
-void tuning_candidates(int effort, int max_tsteps, int precision, int chi_law, int nx, int ny,
+// full grid (tsteps in {1,2,3,4,6,8}, at most 3 for Runge-Kutta, rows in
+// 8..256, prefetch 2 or 4); both add, per depth, the rows that fill 1..8 whole
+// rounds of resident wavefronts.
+void tuning_candidates(int effort, int precision, int chi_law, int integrator, int nx, int ny,
                        Tuning *out, int *n, int cap);
 
-// Autotune cache: one JSON object per line, keyed by device, grid, precision
-// and sensitivity law.  Path from KC_AUTOTUNE_CACHE, else none.
-bool cache_lookup(const char *key, Tuning *t);
+// Autotune cache: one JSON object per line, keyed by device, grid, precision,
+// sensitivity law and (for Runge-Kutta) integrator.  Path from KC_AUTOTUNE_CACHE, else none.
+bool cache_lookup(const char *key, int integrator, Tuning *t);
 void cache_store(const char *key, const Tuning &t, double gcells);
-int device_key(char *buf, size_t n, int nx, int ny, int precision, int chi_law);
+int device_key(char *buf, size_t n, int nx, int ny, int precision, int chi_law, int integrator);
 
 // Diagnostics: partial sums over row blocks (4 doubles each), then one
 // fixed-order final pass writing {t, mass, nutrient, envelope radius, area

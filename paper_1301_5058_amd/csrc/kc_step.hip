@@ -1,26 +1,18 @@
 // kc_step.hip -- explicit time-step kernels of the single-instance solver.
 //
-// step_ref     one step per launch, one thread per cell, neighbours read from
-//              global memory.  The plain form of the stencil; every other
-//              kernel must reproduce its bits.
-// step_stream  T steps per launch: each wavefront advances one strip with
-//              stream_strip (kc_stream.h); strips are numbered x-fastest and
-//              grouped four to a workgroup, and workgroups are remapped so each
-//              XCD owns a contiguous band of strips.
-#include "kc_internal.h"
-#include "kc_stream.h"
+// step_ref     one forward-Euler step per launch, one thread per cell,
+//              neighbours read from global memory; with AVG the result is
+//              averaged with a second input level (the last stage of a
+//              two-stage Runge-Kutta step).  The plain form of the stencil;
+//              every other kernel must reproduce its bits.
+// step_stream  T levels per launch (T Euler steps, or T / 2 Runge-Kutta steps
+//              with RK): each wavefront advances one strip with stream_strip
+//              (kc_stream.h); strips are numbered x-fastest and grouped four to
+//              a workgroup, and workgroups are remapped so each XCD owns a
+//              contiguous band of strips.
+#include "kc_step_kernels.h"
 
 namespace kc {
-
-template <typename R> struct StepArgs {
-    const R *b_in, *n_in, *sg;
-    R *b_out, *n_out;
-    int nx, ny, pitch;
-    int rows;           // output rows per strip
-    int nsx, nstrips;   // strips along x, total strips
-    int nblocks_padded; // grid size (multiple of 8)
-    Coef<R> c;
-};
 
 // ---------------------------------------------------------------------------
 // Reference kernel
@@ -39,7 +31,7 @@ __device__ __forceinline__ void ref_cell(const StepArgs<R> &a, int x, int y, R &
     coef<R, LAW>(sh, n, b, a.c.chi2, D, X);
 }
 
-template <typename R, int LAW>
+template <typename R, int LAW, bool AVG>
 __global__ __launch_bounds__(256) void step_ref(StepArgs<R> a)
 {
     const int x = blockIdx.x * 64 + (threadIdx.x & 63);
@@ -62,59 +54,41 @@ __global__ __launch_bounds__(256) void step_ref(StepArgs<R> a)
     R bo, no;
     update<R>(bP, nP, Fb, Fn, a.c, bo, no);
     const size_t p = (size_t)y * a.pitch + x;
+    if (AVG) {
+        bo = rk2_average<R>(a.b_avg[p], bo);
+        no = rk2_average<R>(a.n_avg[p], no);
+    }
     a.b_out[p] = bo;
     a.n_out[p] = no;
 }
 
 // ---------------------------------------------------------------------------
-// Fused kernel
-// ---------------------------------------------------------------------------
-template <typename R, int T, int LAW, int PF>
-__global__ __launch_bounds__(256) void step_stream(StepArgs<R> a)
-{
-    const int lb = xcd_block(a.nblocks_padded);
-    // wave-uniform by construction; readfirstlane lets the compiler keep the strip
-    // geometry and every row test in scalar registers
-    const int strip = __builtin_amdgcn_readfirstlane(lb * 4 + (int)(threadIdx.x >> 6));
-    if (strip >= a.nstrips)
-        return; // whole wavefront leaves together
-    StripArgs<R> sa;
-    sa.b_in = a.b_in;
-    sa.n_in = a.n_in;
-    sa.sg = a.sg;
-    sa.b_out = a.b_out;
-    sa.n_out = a.n_out;
-    sa.nx = a.nx;
-    sa.ny = a.ny;
-    sa.pitch = a.pitch;
-    sa.rows = a.rows;
-    sa.c = a.c;
-    sa.b_thr = sa.cx = sa.cy = 0.0;
-    const int sx = strip % a.nsx, sy = strip / a.nsx;
-    if (strip_interior<R, T>(sa, sx, sy))
-        stream_strip<R, T, LAW, PF, false>(sa, sx, sy);
-    else
-        stream_strip<R, T, LAW, PF, true>(sa, sx, sy);
-}
-
-// ---------------------------------------------------------------------------
 // Host launchers
 // ---------------------------------------------------------------------------
-static const int kDepths[] = {1, 2, 3, 4, 6, 8};
+static const int kDepths[] = {1, 2, 3, 4, 6, 8}; // Euler steps per launch
+static const int kRkDepths[] = {1, 2, 3};         // Runge-Kutta steps (2 levels each)
 
-int stream_depth_at_most(int t)
+int stream_depth_at_most(int t, int integrator)
 {
     int best = 1;
-    for (int d : kDepths)
-        if (d <= t)
-            best = d;
+    if (integrator == 0) {
+        for (int d : kDepths)
+            if (d <= t)
+                best = d;
+    } else {
+        for (int d : kRkDepths)
+            if (d <= t)
+                best = d;
+    }
     return best;
 }
 
-StreamGeom stream_geom(int precision, int tsteps, int nx, int ny, int rows)
+int stream_levels(int integrator, int tsteps) { return integrator == 0 ? tsteps : 2 * tsteps; }
+
+StreamGeom stream_geom(int precision, int levels, int nx, int ny, int rows)
 {
     const int vec = precision == 0 ? 4 : 2;
-    const int hx = (tsteps + vec - 1) / vec * vec;
+    const int hx = (levels + vec - 1) / vec * vec;
     StreamGeom g;
     g.out_cols = 64 * vec - 2 * hx;
     g.nsx = (nx + g.out_cols - 1) / g.out_cols;
@@ -134,6 +108,7 @@ static StepArgs<R> make_args(const Fields<R> &f, const Coef<R> &c)
     a.sg = f.sg;
     a.b_out = f.b_out;
     a.n_out = f.n_out;
+    a.b_avg = a.n_avg = nullptr;
     a.nx = f.nx;
     a.ny = f.ny;
     a.pitch = f.pitch;
@@ -143,61 +118,60 @@ static StepArgs<R> make_args(const Fields<R> &f, const Coef<R> &c)
     return a;
 }
 
-template <typename R, int T, int LAW>
-static hipError_t launch_stream_pf(const StepArgs<R> &a, int pf, dim3 grid, hipStream_t s)
+template <typename R>
+static const void *stream_kernel(int chi_law, int integrator, int levels, int pf)
 {
-    if (pf == 4)
-        hipLaunchKernelGGL((step_stream<R, T, LAW, 4>), grid, dim3(256), 0, s, a);
-    else
-        hipLaunchKernelGGL((step_stream<R, T, LAW, 2>), grid, dim3(256), 0, s, a);
-    return hipGetLastError();
-}
-
-template <typename R, int LAW>
-static hipError_t launch_stream_t(const StepArgs<R> &a, int T, int pf, dim3 grid, hipStream_t s)
-{
-    switch (T) {
-    case 1: return launch_stream_pf<R, 1, LAW>(a, pf, grid, s);
-    case 2: return launch_stream_pf<R, 2, LAW>(a, pf, grid, s);
-    case 3: return launch_stream_pf<R, 3, LAW>(a, pf, grid, s);
-    case 4: return launch_stream_pf<R, 4, LAW>(a, pf, grid, s);
-    case 6: return launch_stream_pf<R, 6, LAW>(a, pf, grid, s);
-    case 8: return launch_stream_pf<R, 8, LAW>(a, pf, grid, s);
-    default: return hipErrorInvalidValue;
-    }
+    if ((pf != 2 && pf != 4) || (integrator != 0 && integrator != 1) ||
+        (chi_law != 0 && chi_law != 1))
+        return nullptr;
+    return integrator == 0 ? stream_kernel_for<R, false>(chi_law, levels, pf)
+                           : stream_kernel_for<R, true>(chi_law, levels, pf);
 }
 
 template <typename R>
-hipError_t launch_stream(const Fields<R> &f, const Coef<R> &c, int chi_law, const Tuning &t,
-                         hipStream_t s)
+hipError_t launch_stream(const Fields<R> &f, const Coef<R> &c, int chi_law, int integrator,
+                         const Tuning &t, hipStream_t s)
 {
+    const int levels = stream_levels(integrator, t.tsteps);
+    const void *fn = stream_kernel<R>(chi_law, integrator, levels, t.prefetch);
+    if (!fn || t.rows < 1)
+        return hipErrorInvalidValue;
     StepArgs<R> a = make_args(f, c);
-    const StreamGeom g = stream_geom(sizeof(R) == 4 ? 0 : 1, t.tsteps, f.nx, f.ny, t.rows);
+    const StreamGeom g = stream_geom(sizeof(R) == 4 ? 0 : 1, levels, f.nx, f.ny, t.rows);
     a.rows = t.rows;
     a.nsx = g.nsx;
     a.nstrips = g.nstrips;
     a.nblocks_padded = g.nblocks_padded;
-    const dim3 grid(g.nblocks_padded);
-    if (chi_law == 0)
-        return launch_stream_t<R, 0>(a, t.tsteps, t.prefetch, grid, s);
-    return launch_stream_t<R, 1>(a, t.tsteps, t.prefetch, grid, s);
+    void *args[] = {&a};
+    return hipLaunchKernel(fn, dim3(g.nblocks_padded), dim3(256), args, 0, s);
 }
 
 template <typename R>
-hipError_t launch_ref(const Fields<R> &f, const Coef<R> &c, int chi_law, hipStream_t s)
+hipError_t launch_ref(const Fields<R> &f, const Coef<R> &c, int chi_law, hipStream_t s,
+                      const R *b_avg, const R *n_avg)
 {
-    const StepArgs<R> a = make_args(f, c);
+    StepArgs<R> a = make_args(f, c);
+    a.b_avg = b_avg;
+    a.n_avg = n_avg;
     const dim3 grid((f.nx + 63) / 64, (f.ny + 3) / 4);
-    if (chi_law == 0)
-        hipLaunchKernelGGL((step_ref<R, 0>), grid, dim3(256), 0, s, a);
-    else
-        hipLaunchKernelGGL((step_ref<R, 1>), grid, dim3(256), 0, s, a);
+    const bool avg = b_avg != nullptr;
+    if (chi_law == 0) {
+        if (avg)
+            hipLaunchKernelGGL((step_ref<R, 0, true>), grid, dim3(256), 0, s, a);
+        else
+            hipLaunchKernelGGL((step_ref<R, 0, false>), grid, dim3(256), 0, s, a);
+    } else {
+        if (avg)
+            hipLaunchKernelGGL((step_ref<R, 1, true>), grid, dim3(256), 0, s, a);
+        else
+            hipLaunchKernelGGL((step_ref<R, 1, false>), grid, dim3(256), 0, s, a);
+    }
     return hipGetLastError();
 }
 
 template <typename R>
-hipError_t time_stream(const Fields<R> &f, const Coef<R> &c, int chi_law, const Tuning &t,
-                       hipStream_t s, int reps, double *ms)
+hipError_t time_stream(const Fields<R> &f, const Coef<R> &c, int chi_law, int integrator,
+                       const Tuning &t, hipStream_t s, int reps, double *ms)
 {
     hipEvent_t e0, e1;
     hipError_t e = hipEventCreate(&e0);
@@ -208,11 +182,11 @@ hipError_t time_stream(const Fields<R> &f, const Coef<R> &c, int chi_law, const 
         (void)hipEventDestroy(e0);
         return e;
     }
-    e = launch_stream<R>(f, c, chi_law, t, s);
+    e = launch_stream<R>(f, c, chi_law, integrator, t, s);
     if (e == hipSuccess)
         e = hipEventRecord(e0, s);
     for (int i = 0; i < reps && e == hipSuccess; ++i)
-        e = launch_stream<R>(f, c, chi_law, t, s);
+        e = launch_stream<R>(f, c, chi_law, integrator, t, s);
     if (e == hipSuccess)
         e = hipEventRecord(e1, s);
     if (e == hipSuccess)
@@ -227,56 +201,33 @@ hipError_t time_stream(const Fields<R> &f, const Coef<R> &c, int chi_law, const 
     return e;
 }
 
-template <typename R, int T, int LAW, int PF> static int blocks_per_cu()
-{
-    int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, step_stream<R, T, LAW, PF>, 256, 0) !=
-        hipSuccess)
-        return 0;
-    return nb;
-}
-
-template <typename R, int LAW> static int blocks_per_cu_t(int T, int pf)
-{
-    switch (T) {
-    case 1: return pf == 4 ? blocks_per_cu<R, 1, LAW, 4>() : blocks_per_cu<R, 1, LAW, 2>();
-    case 2: return pf == 4 ? blocks_per_cu<R, 2, LAW, 4>() : blocks_per_cu<R, 2, LAW, 2>();
-    case 3: return pf == 4 ? blocks_per_cu<R, 3, LAW, 4>() : blocks_per_cu<R, 3, LAW, 2>();
-    case 4: return pf == 4 ? blocks_per_cu<R, 4, LAW, 4>() : blocks_per_cu<R, 4, LAW, 2>();
-    case 6: return pf == 4 ? blocks_per_cu<R, 6, LAW, 4>() : blocks_per_cu<R, 6, LAW, 2>();
-    case 8: return pf == 4 ? blocks_per_cu<R, 8, LAW, 4>() : blocks_per_cu<R, 8, LAW, 2>();
-    default: return 0;
-    }
-}
-
-int resident_waves(int precision, int chi_law, int tsteps, int prefetch)
+int resident_waves(int precision, int chi_law, int integrator, int tsteps, int prefetch)
 {
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         return 0;
-    int nb;
-    if (precision == 0)
-        nb = chi_law == 0 ? blocks_per_cu_t<float, 0>(tsteps, prefetch)
-                          : blocks_per_cu_t<float, 1>(tsteps, prefetch);
-    else
-        nb = chi_law == 0 ? blocks_per_cu_t<double, 0>(tsteps, prefetch)
-                          : blocks_per_cu_t<double, 1>(tsteps, prefetch);
+    const int levels = stream_levels(integrator, tsteps);
+    const void *fn = precision == 0 ? stream_kernel<float>(chi_law, integrator, levels, prefetch)
+                                    : stream_kernel<double>(chi_law, integrator, levels, prefetch);
+    int nb = 0;
+    if (!fn || hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, 256, 0) != hipSuccess)
+        return 0;
     return nb * 4 * cus;
 }
 
-int round_fitted_rows(int precision, int tsteps, int nx, int ny, int waves, int rounds)
+int round_fitted_rows(int precision, int levels, int nx, int ny, int waves, int rounds)
 {
     if (waves <= 0 || rounds <= 0 || nx <= 0 || ny <= 0)
         return 0;
-    const StreamGeom g = stream_geom(precision, tsteps, nx, ny, 1);
+    const StreamGeom g = stream_geom(precision, levels, nx, ny, 1);
     const long m = (long)waves * rounds / g.nsx; // strip rows that fill `rounds` rounds
     if (m <= 0)
         return 0;
     return (int)((ny + m - 1) / m);
 }
 
-void tuning_candidates(int effort, int max_tsteps, int precision, int chi_law, int nx, int ny,
+void tuning_candidates(int effort, int precision, int chi_law, int integrator, int nx, int ny,
                        Tuning *out, int *n, int cap)
 {
     static const int quick_t[] = {1, 2, 3, 4};
@@ -286,6 +237,7 @@ void tuning_candidates(int effort, int max_tsteps, int precision, int chi_law, i
     const int *ts = effort ? full_t : quick_t;
     const int *rs = effort ? full_r : quick_r;
     const int nt = effort ? 6 : 4, nr = effort ? 10 : 4;
+    const int max_t = integrator == 0 ? 8 : 3;
     int k = 0;
     auto add = [&](int t, int r, int p) {
         for (int i = 0; i < k && i < cap; ++i)
@@ -299,7 +251,7 @@ void tuning_candidates(int effort, int max_tsteps, int precision, int chi_law, i
         ++k;
     };
     for (int i = 0; i < nt; ++i) {
-        if (ts[i] > max_tsteps)
+        if (ts[i] > max_t)
             continue;
         for (int p = 0; p < (effort ? 2 : 1); ++p) {
             const int pf = p ? 2 : 4;
@@ -308,9 +260,10 @@ void tuning_candidates(int effort, int max_tsteps, int precision, int chi_law, i
             // rows that fill a whole number of rounds of resident wavefronts
             if (nx <= 0 || ny <= 0)
                 continue;
-            const int w = resident_waves(precision, chi_law, ts[i], pf);
+            const int w = resident_waves(precision, chi_law, integrator, ts[i], pf);
             for (int q = 1; q <= 8; ++q) {
-                const int r = round_fitted_rows(precision, ts[i], nx, ny, w, q);
+                const int r = round_fitted_rows(precision, stream_levels(integrator, ts[i]), nx,
+                                                ny, w, q);
                 if (r >= 4 && r <= 512)
                     add(ts[i], r, pf);
             }
@@ -319,16 +272,17 @@ void tuning_candidates(int effort, int max_tsteps, int precision, int chi_law, i
     *n = k < cap ? k : cap;
 }
 
-template hipError_t time_stream<float>(const Fields<float> &, const Coef<float> &, int,
+template hipError_t time_stream<float>(const Fields<float> &, const Coef<float> &, int, int,
                                        const Tuning &, hipStream_t, int, double *);
-template hipError_t time_stream<double>(const Fields<double> &, const Coef<double> &, int,
+template hipError_t time_stream<double>(const Fields<double> &, const Coef<double> &, int, int,
                                         const Tuning &, hipStream_t, int, double *);
-template hipError_t launch_stream<float>(const Fields<float> &, const Coef<float> &, int,
+template hipError_t launch_stream<float>(const Fields<float> &, const Coef<float> &, int, int,
                                          const Tuning &, hipStream_t);
-template hipError_t launch_stream<double>(const Fields<double> &, const Coef<double> &, int,
+template hipError_t launch_stream<double>(const Fields<double> &, const Coef<double> &, int, int,
                                           const Tuning &, hipStream_t);
-template hipError_t launch_ref<float>(const Fields<float> &, const Coef<float> &, int, hipStream_t);
+template hipError_t launch_ref<float>(const Fields<float> &, const Coef<float> &, int, hipStream_t,
+                                      const float *, const float *);
 template hipError_t launch_ref<double>(const Fields<double> &, const Coef<double> &, int,
-                                       hipStream_t);
+                                       hipStream_t, const double *, const double *);
 
 } // namespace kc

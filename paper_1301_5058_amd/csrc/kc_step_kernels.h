@@ -1,0 +1,58 @@
+// kc_step_kernels.h -- the fused step kernel and its launch arguments, shared
+// by the translation units that instantiate it (kc_stream_*.hip) and the host
+// launchers (kc_step.hip).
+#pragma once
+
+#include "kc_internal.h"
+#include "kc_stream.h"
+
+namespace kc {
+
+template <typename R> struct StepArgs {
+    const R *b_in, *n_in, *sg;
+    R *b_out, *n_out;
+    const R *b_avg, *n_avg; // step_ref with AVG: the level averaged with
+    int nx, ny, pitch;
+    int rows;           // output rows per strip
+    int nsx, nstrips;   // strips along x, total strips
+    int nblocks_padded; // grid size (multiple of 8)
+    Coef<R> c;
+};
+
+// ---------------------------------------------------------------------------
+// Fused kernel
+// ---------------------------------------------------------------------------
+template <typename R, int T, int LAW, int PF, bool RK>
+__global__ __launch_bounds__(256) void step_stream(StepArgs<R> a)
+{
+    const int lb = xcd_block(a.nblocks_padded);
+    // wave-uniform by construction; readfirstlane lets the compiler keep the strip
+    // geometry and every row test in scalar registers
+    const int strip = __builtin_amdgcn_readfirstlane(lb * 4 + (int)(threadIdx.x >> 6));
+    if (strip >= a.nstrips)
+        return; // whole wavefront leaves together
+    StripArgs<R> sa;
+    sa.b_in = a.b_in;
+    sa.n_in = a.n_in;
+    sa.sg = a.sg;
+    sa.b_out = a.b_out;
+    sa.n_out = a.n_out;
+    sa.nx = a.nx;
+    sa.ny = a.ny;
+    sa.pitch = a.pitch;
+    sa.rows = a.rows;
+    sa.c = a.c;
+    sa.b_thr = sa.cx = sa.cy = 0.0;
+    const int sx = strip % a.nsx, sy = strip / a.nsx;
+    if (strip_interior<R, T>(sa, sx, sy))
+        stream_strip<R, T, LAW, PF, false, RK>(sa, sx, sy);
+    else
+        stream_strip<R, T, LAW, PF, true, RK>(sa, sx, sy);
+}
+
+// The compiled fused kernel of precision R and integrator RK for (law, levels,
+// prefetch), or null when there is none.  Each (R, RK) pair is defined in a
+// translation unit of its own (kc_stream_<precision>_<integrator>.hip).
+template <typename R, bool RK> const void *stream_kernel_for(int chi_law, int levels, int pf);
+
+} // namespace kc

@@ -11,6 +11,12 @@
 // launch: read b, n, sigma once, write b', n' once, plus halo re-reads that
 // mostly hit L2.
 //
+// With RK, each time step is two levels of the two-stage Runge-Kutta method
+// u' = (u + E(E(u))) / 2 (E = one forward-Euler step): an even level hands the
+// u of its centre row to the next level together with its Euler output, and
+// the odd level averages that u with its own Euler output.  A block of T
+// levels then advances T / 2 steps.
+//
 // Level L (0-based) computes only the centre rows [y0 - T + L, y1 + T - 1 - L):
 // the rows that the T-th level's output rows [y0, y1) depend on, plus one lead-in
 // row whose only purpose is the face flux below the first needed row.  The test
@@ -75,9 +81,10 @@ __device__ __forceinline__ bool strip_interior(const StripArgs<R> &a, int sx, in
     return xl >= 0 && xl + WC <= a.nx - 1 && y0 >= T && y1 + T <= a.ny;
 }
 
-template <typename R, int T, int LAW, int PF, bool CHECK>
+template <typename R, int T, int LAW, int PF, bool CHECK, bool RK = false>
 __device__ __forceinline__ void stream_strip(const StripArgs<R> &a, int sx, int sy)
 {
+    static_assert(!RK || T % 2 == 0, "a two-stage Runge-Kutta block has an even level count");
     constexpr int VEC = StreamShape<R>::VEC;
     constexpr int HX = Halo<T, VEC>::HX;
     constexpr int WC = Halo<T, VEC>::WC;
@@ -96,13 +103,17 @@ __device__ __forceinline__ void stream_strip(const StripArgs<R> &a, int sx, int 
     for (int k = 0; k < VEC; ++k)
         ve[k] = !CHECK || ((x0 + k >= 0) && (x0 + k + 1 < a.nx));
 
-    // level state: centre row of level L and the face inflow G(S,P) below it
+    // level state: centre row of level L and the face inflow G(S,P) below it;
+    // with RK, the second level of each step also holds the step's input u of
+    // its centre row (cub, cun)
     R cb[T][VEC], cn[T][VEC], cD[T][VEC], cX[T][VEC], cs[T][VEC], fb[T][VEC], fn[T][VEC];
+    R cub[T][VEC], cun[T][VEC];
 #pragma unroll
     for (int L = 0; L < T; ++L)
 #pragma unroll
         for (int k = 0; k < VEC; ++k)
-            cb[L][k] = cn[L][k] = cD[L][k] = cX[L][k] = cs[L][k] = fb[L][k] = fn[L][k] = R(0);
+            cb[L][k] = cn[L][k] = cD[L][k] = cX[L][k] = cs[L][k] = fb[L][k] = fn[L][k] =
+                cub[L][k] = cun[L][k] = R(0);
 
     // Prefetch ring: slot (row - rs) % PF.  Loads are unconditional, from
     // addresses clamped into the array: a row past the last input row or a
@@ -125,18 +136,20 @@ __device__ __forceinline__ void stream_strip(const StripArgs<R> &a, int sx, int 
 
     // One group of PF rows.  With FULL every level is active on every row of
     // the group (the steady state), so the body is one straight-line block.
-    auto group = [&](int r0, auto full_tag) __attribute__((always_inline)) {
+    auto group = [&](int r0, auto full_tag) {
         constexpr bool FULL = decltype(full_tag)::value;
 #pragma unroll
         for (int u = 0; u < PF; ++u) {
             const int row = r0 + u;
             // consume slot u (row), refill it with row + PF
             R ib[VEC], in[VEC], iD[VEC], iX[VEC], is[VEC];
+            R iub[VEC], iun[VEC]; // RK: u of the incoming row of an odd level
 #pragma unroll
             for (int k = 0; k < VEC; ++k) {
                 ib[k] = pb[u][k];
                 in[k] = pn[u][k];
                 is[k] = R(0.5) * ps[u][k];
+                iub[k] = iun[k] = R(0);
             }
             load_row(row + PF, pb[u], pn[u], ps[u]);
 #pragma unroll
@@ -150,6 +163,14 @@ __device__ __forceinline__ void stream_strip(const StripArgs<R> &a, int sx, int 
                     // outside this level's rows: only move the incoming row in
 #pragma unroll
                     for (int k = 0; k < VEC; ++k) {
+                        if (RK && L % 2 == 0) {
+                            iub[k] = cb[L][k];
+                            iun[k] = cn[L][k];
+                        }
+                        if (RK && L % 2 == 1) {
+                            cub[L][k] = iub[k];
+                            cun[L][k] = iun[k];
+                        }
                         cb[L][k] = ib[k];
                         cn[L][k] = in[k];
                         cD[L][k] = iD[k];
@@ -182,6 +203,24 @@ __device__ __forceinline__ void stream_strip(const StripArgs<R> &a, int sx, int 
                     const R Fn = net<R>(gen[k], k ? gen[k - 1] : wn, gvn[k], fn[L][k]);
                     update<R>(cb[L][k], cn[L][k], Fb, Fn, a.c, ob[k], on[k]);
                     os[k] = cs[L][k];
+                }
+                if (RK && L % 2 == 1) {
+                    // second stage: the step's result is the average of its input u
+                    // and the two chained Euler stages
+#pragma unroll
+                    for (int k = 0; k < VEC; ++k) {
+                        ob[k] = rk2_average<R>(cub[L][k], ob[k]);
+                        on[k] = rk2_average<R>(cun[L][k], on[k]);
+                        cub[L][k] = iub[k];
+                        cun[L][k] = iun[k];
+                    }
+                }
+                if (RK && L % 2 == 0) {
+#pragma unroll
+                    for (int k = 0; k < VEC; ++k) {
+                        iub[k] = cb[L][k];
+                        iun[k] = cn[L][k];
+                    }
                 }
 #pragma unroll
                 for (int k = 0; k < VEC; ++k) {

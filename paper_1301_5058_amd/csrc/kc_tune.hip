@@ -14,7 +14,7 @@
 
 namespace kc {
 
-int device_key(char *buf, size_t n, int nx, int ny, int precision, int chi_law)
+int device_key(char *buf, size_t n, int nx, int ny, int precision, int chi_law, int integrator)
 {
     int dev = 0;
     hipDeviceProp_t prop;
@@ -26,13 +26,14 @@ int device_key(char *buf, size_t n, int nx, int ny, int precision, int chi_law)
     for (char *p = a; *p; ++p)
         if (*p == '"' || *p == '|' || *p == ' ')
             *p = '_';
-    return snprintf(buf, n, "%s|%dx%d|%s|%s", a, nx, ny, precision == 0 ? "fp32" : "fp64",
-                    chi_law == 0 ? "receptor" : "constant");
+    // forward-Euler keys carry no integrator field; Runge-Kutta keys end in "|rk2"
+    return snprintf(buf, n, "%s|%dx%d|%s|%s%s", a, nx, ny, precision == 0 ? "fp32" : "fp64",
+                    chi_law == 0 ? "receptor" : "constant", integrator == 0 ? "" : "|rk2");
 }
 
 static const char *cache_path() { return getenv("KC_AUTOTUNE_CACHE"); }
 
-bool cache_lookup(const char *key, Tuning *t)
+bool cache_lookup(const char *key, int integrator, Tuning *t)
 {
     const char *path = cache_path();
     if (!path || !*path)
@@ -53,7 +54,7 @@ bool cache_lookup(const char *key, Tuning *t)
         if (pt && pr && pp && sscanf(pt, "\"tsteps\": %d", &T) == 1 &&
             sscanf(pr, "\"rows\": %d", &R) == 1 && sscanf(pp, "\"prefetch\": %d", &P) == 1 &&
             T >= 1 && T <= 8 && R >= 1 && (P == 2 || P == 4)) {
-            t->tsteps = stream_depth_at_most(T);
+            t->tsteps = stream_depth_at_most(T, integrator);
             t->rows = R;
             t->prefetch = P;
             found = true;

@@ -15,6 +15,7 @@ KC_OK, KC_EINVAL, KC_ENONFINITE, KC_EUNSTABLE, KC_ESTATE, KC_ENOMEM, KC_EHIP = 0
 KC_FP32, KC_FP64 = 0, 1
 KC_CHI_RECEPTOR, KC_CHI_CONSTANT = 0, 1
 KC_MEM_HOST, KC_MEM_DEVICE = 0, 1
+KC_EULER, KC_RK2 = 0, 1
 
 c_int32, c_int64, c_double, c_void_p = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
 P_double = ctypes.POINTER(c_double)
@@ -27,7 +28,7 @@ class KcGrid(ctypes.Structure):
 class KcParams(ctypes.Structure):
     _fields_ = [("D_n", c_double), ("theta", c_double), ("kappa", c_double), ("chi", c_double),
                 ("chi_law", c_int32), ("precision", c_int32), ("b_thr", c_double),
-                ("cx", c_double), ("cy", c_double), ("step0", c_int64)]
+                ("cx", c_double), ("cy", c_double), ("step0", c_int64), ("integrator", c_int32)]
 
 
 class KbInstance(ctypes.Structure):

@@ -24,7 +24,7 @@ def _torch_dtype(precision):
 class Solver:
     def __init__(self, nx, ny, h=1.0, dt=0.2, chi=0.0, chi_law="receptor", precision="fp32",
                  D_n=1.0, theta=1.0, kappa=1.0, b_thr=0.5, cx=None, cy=None, step0=0,
-                 stream=None):
+                 stream=None, integrator="euler"):
         self.nx, self.ny, self.h, self.dt = int(nx), int(ny), float(h), float(dt)
         p = N.default_params()
         p.D_n, p.theta, p.kappa, p.chi = float(D_n), float(theta), float(kappa), float(chi)
@@ -34,6 +34,9 @@ class Solver:
         p.cx = math.nan if cx is None else float(cx)
         p.cy = math.nan if cy is None else float(cy)
         p.step0 = int(step0)
+        if integrator not in ("euler", "rk2"):
+            raise ValueError("integrator must be 'euler' or 'rk2'")
+        p.integrator = N.KC_EULER if integrator == "euler" else N.KC_RK2
         self.precision = p.precision
         if stream is None:
             stream = torch.cuda.current_stream()

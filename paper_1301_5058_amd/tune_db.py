@@ -18,11 +18,12 @@ import torch
 from . import workload
 from .solver import Solver
 
-GRIDS = [  # (nx, n0, a, chi, precision)
-    (128, 0.8, 0.5, 0.5, "fp32"), (128, 0.8, 0.5, 0.5, "fp64"),
-    (512, 0.35, 0.5, 2.0, "fp32"),
-    (4096, 0.5, 0.5, 1.0, "fp32"), (4096, 0.5, 0.5, 1.0, "fp64"),
-    (16384, 0.35, 0.5, 2.0, "fp32"),
+GRIDS = [  # (nx, n0, a, chi, precision, integrator)
+    (128, 0.8, 0.5, 0.5, "fp32", "euler"), (128, 0.8, 0.5, 0.5, "fp64", "euler"),
+    (512, 0.35, 0.5, 2.0, "fp32", "euler"),
+    (4096, 0.5, 0.5, 1.0, "fp32", "euler"), (4096, 0.5, 0.5, 1.0, "fp64", "euler"),
+    (16384, 0.35, 0.5, 2.0, "fp32", "euler"),
+    (4096, 0.5, 0.5, 1.0, "fp32", "rk2"), (4096, 0.5, 0.5, 1.0, "fp64", "rk2"),
 ]
 
 
@@ -32,16 +33,16 @@ def main():
     ap.add_argument("--effort", type=int, default=1)
     a = ap.parse_args()
     os.environ["KC_AUTOTUNE_CACHE"] = os.path.abspath(a.out)
-    for nx, n0, amp, chi, prec in GRIDS:
+    for nx, n0, amp, chi, prec, integ in GRIDS:
         b, n, s = workload.fields(nx, nx, n0, amp, 0)
         dt = workload.config_dt(b, n, s)
         if prec == "fp64":
             b, n, s = (x.astype(np.float64) for x in (b, n, s))
-        S = Solver(nx, nx, dt=dt, chi=chi, precision=prec)
+        S = Solver(nx, nx, dt=dt, chi=chi, precision=prec, integrator=integ)
         S.set_fields(*(torch.from_numpy(x).cuda() for x in (b, n, s)))
         g = S.autotune(effort=a.effort, use_cache=True)
-        print("%5d^2 %s: tsteps=%d rows=%d prefetch=%d  %.1f GCell/s" % ((nx, prec) + S.tuning() + (g,)),
-              flush=True)
+        print("%5d^2 %s %s: tsteps=%d rows=%d prefetch=%d  %.1f GCell/s"
+              % ((nx, prec, integ) + S.tuning() + (g,)), flush=True)
         S.close()
     return 0
 

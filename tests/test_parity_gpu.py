@@ -218,14 +218,15 @@ def test_error_paths():
 # ----------------------------------------------------------------------------
 # Full-size workloads in the benchmark's launch configuration: sampled cells
 # ----------------------------------------------------------------------------
-def _oracle_cell(b, n, s, dt, steps, j, i, **kw):
+def _oracle_cell(b, n, s, dt, steps, j, i, reach=1, **kw):
     """Oracle value of cell (j, i) after `steps` steps, from the window of
-    cells within `steps + 1` of it (cells farther away cannot reach it)."""
+    cells within `reach * steps + 1` of it (cells farther away cannot reach
+    it; reach = Euler stages per step)."""
     ny, nx = b.shape
-    w = steps + 1
+    w = reach * steps + 1
     j0, j1, i0, i1 = max(0, j - w), min(ny, j + w + 1), max(0, i - w), min(nx, i + w + 1)
-    # a window edge inside the domain acts as a wall; it is more than `steps`
-    # cells away from (j, i), so the value at (j, i) is exact.
+    # a window edge inside the domain acts as a wall; it is more than
+    # `reach * steps` cells away from (j, i), so the value at (j, i) is exact.
     wb, wn = oracle.run(b[j0:j1, i0:i1], n[j0:j1, i0:i1], s[j0:j1, i0:i1], 1.0, dt, steps, **kw)
     return wb[j - j0, i - i0], wn[j - j0, i - i0]
 
