@@ -15,8 +15,8 @@ timed region.  Prints one JSON line.
 The line also carries, under "extras", the other workloads of the solver:
 the FP64 variant, chi = 0 and the two-stage Runge-Kutta integrator (FP32 and
 FP64) at 4096^2, the 16384^2 grid (20,000 steps), the 256-instance batched
-sweep (30,000 steps, one persistent launch), and the velocity map (surrogate
-with solver fallback).  --no-extras skips them.
+sweep (30,000 steps), the velocity map (surrogate with solver fallback) and
+the 1-D front-speed experiment of Sec. 4.2.  --no-extras skips them.
 """
 import argparse
 import hashlib
@@ -365,7 +365,21 @@ def extras(args):
     progress("sweep: %s" % ex["sweep_256"])
     ex["velocity_map"] = velocity_map.run_velocity_map()
     progress("velocity map: %s" % ex["velocity_map"])
+    ex["front1d"] = front1d_speeds()
+    progress("1-D fronts: %s" % ex["front1d"])
     return ex
+
+
+def front1d_speeds():
+    """The 1-D front experiment of Sec. 4.2: 30 (n0, chi0) grids in one batch,
+    front speeds against the closed-form bound c-bar."""
+    from paper_1301_5058_amd import front1d
+    r = front1d.run_front1d()
+    rows = [{"n0": p[0], "chi0": p[1], "v": round(float(v), 5), "cbar": round(float(cb), 5),
+             "v_over_cbar": round(float(v / cb), 4)}
+            for p, v, cb in zip(r["points"], r["velocity"], r["cbar"])]
+    return {"cells": r["cells"], "steps": r["steps"], "window": list(r["window"]),
+            "gpu_s": round(r["gpu_s"], 3), "wall_s": round(r["wall_s"], 3), "fronts": rows}
 
 
 def main():

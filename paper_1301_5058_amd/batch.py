@@ -1,8 +1,8 @@
 """Python face of the batched sweep (kb_* calls of include/kb.h).
 
 Batch wraps one kb_batch: many FP32 instances of the solver with their own
-grid, time step, rates and agar field, advanced together by one persistent
-launch per run(); the envelope radius R(t), mass and nutrient of every
+grid, time step, rates and agar field, advanced together by one launch per
+time block; the envelope radius R(t), mass and nutrient of every
 instance are sampled on the device, and fit_velocity() returns dR/dt per
 instance.  Every computation happens in libkc.so.
 """

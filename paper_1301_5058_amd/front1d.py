@@ -1,0 +1,100 @@
+"""The one-dimensional front-speed experiment of Sec. 4.2 on the batched solver.
+
+For every (n0, chi0) of the experiment one 1 x cells grid on [0, length] runs
+the system velo-system-1d (constant sensitivity, sigma = sigma0): all
+instances in one batch (kb_* calls, per-block launches), the front position
+sampled on the device as the envelope radius about x = 0 (centre at cell
+index -1/2, threshold b_thr = n0 / 2), and its velocity fitted on the device
+over the window of front positions.  The velocities are compared with the
+closed-form bound c-bar(n0, chi0) of Sec. 4.1 (ks_cbar); the speeds over the
+two halves of the window tell a steady front from one that still changes
+speed (slow fronts that deplete the nutrient ahead of them decelerate).  This
+module only
+chooses instances and moves arrays; every computation runs in libkc.so.
+"""
+import math
+import time
+
+import numpy as np
+import torch
+
+from . import workload
+from .batch import Batch
+from .surrogate import Surrogate
+
+SAMPLE_EVERY = 100
+
+
+def instances(cells=None, n0s=None, chis=None):
+    """(descriptors, fields) of the experiment's grid of (n0, chi0)."""
+    c = workload.FRONT1D
+    cells = int(cells or c["cells"])
+    n0s = c["n0"] if n0s is None else n0s
+    chis = c["chi"] if chis is None else chis
+    h = c["length"] / cells
+    descs, fields = [], []
+    for n0 in n0s:
+        for chi in chis:
+            b, n, s = workload.front1d_fields(cells, c["length"], n0, c["b_max"], c["r0"], c["cut"],
+                                              c["sigma0"])
+            dt = workload.front1d_dt(cells, c["length"], n0, chi, c["b_max"], c["sigma0"])
+            descs.append(dict(nx=cells, ny=1, h=h, dt=dt, chi=float(chi), b_thr=0.5 * n0,
+                              cx=-0.5, cy=0.0, n0=float(n0)))
+            fields.append((b, n, s))
+    return descs, fields
+
+
+def speed_bounds(points, sigma0=1.0):
+    """c-bar(n0, chi0) sqrt(sigma0) for rows (n0, chi0) from the library (ks_cbar)."""
+    X = np.zeros((len(points), 3), dtype=np.float32)
+    X[:, :2] = np.asarray(points, dtype=np.float32)
+    S = Surrogate(max(1, len(points)))
+    try:
+        return S.cbar(X, sigma0).astype(np.float64)
+    finally:
+        S.close()
+
+
+def steps_needed(descs, cbar, reach, min_speed_frac=0.5):
+    """Steps after which every front has passed `reach`, if it moves at least
+    min_speed_frac of its bound (a multiple of SAMPLE_EVERY)."""
+    t = max(reach / (min_speed_frac * cb) / d["dt"] for d, cb in zip(descs, cbar))
+    return int(math.ceil(t / SAMPLE_EVERY)) * SAMPLE_EVERY
+
+
+def run_front1d(cells=None, n0s=None, chis=None, steps=None):
+    """Run the experiment; returns a dict with the velocities, the bounds and
+    the device time."""
+    c = workload.FRONT1D
+    descs, fields = instances(cells, n0s, chis)
+    pts = [(d["n0"], d["chi"]) for d in descs]
+    cbar = speed_bounds(pts, c["sigma0"])
+    lo, hi = c["window"]
+    if steps is None:
+        steps = steps_needed(descs, cbar, hi)
+    B = Batch(descs, chi_law="constant", max_samples=steps // SAMPLE_EVERY + 1)
+    try:
+        for k, (b, n, s) in enumerate(fields):
+            B.set_fields(k, b, n, s)
+        st = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e0.record(st)
+        B.run(steps, SAMPLE_EVERY)
+        v, npts = B.fit_velocity(lo, hi, radius="envelope")
+        mid = 0.5 * (lo + hi)
+        v1, _ = B.fit_velocity(lo, mid, radius="envelope")
+        v2, _ = B.fit_velocity(mid, hi, radius="envelope")
+        e1.record(st)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        series = B.series()
+    finally:
+        B.close()
+    # a front is steady when its speeds over the two halves of the window agree
+    steady = np.isfinite(v1) & np.isfinite(v2) & (np.abs(v1 - v2) <= 0.1 * np.abs(v))
+    return dict(points=pts, velocity=v, samples=npts, cbar=cbar, steps=steps,
+                velocity_halves=(v1, v2), steady=steady,
+                dt=[d["dt"] for d in descs], cells=descs[0]["nx"], window=(lo, hi),
+                gpu_s=e0.elapsed_time(e1) / 1e3, wall_s=wall, series=series)

@@ -82,3 +82,42 @@ def sweep(count=256, meta_seed=2026, sides=(256, 512, 1024, 2048)):
         a = float(rng.uniform(0.1, 0.5))
         out.append(dict(nx=side, ny=side, n0=n0, chi=chi, a=a, seed=k))
     return out
+
+
+# ---------------------------------------------------------------------------
+# The one-dimensional front experiment (Sec. 4.2, system velo-system-1d):
+# n_t = n_xx - n b,  b_t = (sigma0 n b b_x - chi0 sigma0 n b^2 n_x)_x + n b on
+# [0, 20] with n(x, 0) = n0 and b(x, 0) = b_M exp(-x^2 / 6.25), b_M = 0.71,
+# sigma0 = 1, for n0 in {0.35, 0.71, 1.07, 2, 3, 4} and chi0 in
+# {0, 1, 2.5, 5, 10} (constant sensitivity).  Readings: cell-centred cells
+# x_i = (i + 1/2) h on [0, length]; the inoculum is cut beyond 3 r0 (r0 = 2.5),
+# as in two dimensions, because logistic growth of an uncut tail would reach
+# the threshold ahead of the front; the front position is fitted over
+# x in [9, 17], beyond the initial support.
+# ---------------------------------------------------------------------------
+FRONT1D = dict(length=20.0, cells=400, b_max=0.71, r0=2.5, cut=3.0, sigma0=1.0,
+               n0=(0.35, 0.71, 1.07, 2.0, 3.0, 4.0), chi=(0.0, 1.0, 2.5, 5.0, 10.0),
+               window=(9.0, 17.0))
+
+
+def front1d_fields(cells, length, n0, b_max=0.71, r0=2.5, cut=3.0, sigma0=1.0):
+    """(b0, n0_field, sigma) float32 arrays of shape [1, cells] on [0, length]."""
+    h = length / cells
+    x = (np.arange(cells, dtype=np.float64) + 0.5) * h
+    b = b_max * np.exp(-x * x / (r0 * r0))
+    b[x > cut * r0] = 0.0
+    n = np.full((1, cells), np.float32(n0), dtype=np.float32)
+    s = np.full((1, cells), np.float32(sigma0), dtype=np.float32)
+    return b.astype(np.float32)[None, :], n, s
+
+
+def front1d_dt(cells, length, n0, chi=0.0, b_max=0.71, sigma0=1.0, D_n=1.0, factor=0.2):
+    """dt = factor h^2 / max(D_n, sigma0 n0 (n0 + b_max) (1 + chi n0)), FP32-rounded.
+
+    n stays <= n0 and b <= n0 + b_max, so sigma n b stays below
+    sigma0 n0 (n0 + b_max) for the whole run (the initial fields alone would
+    under-estimate it); the factor (1 + chi n0) covers the chemotactic outflow,
+    chi sigma n b times nutrient differences of up to n0, which the positivity
+    bound of the donor-cell step counts next to the diffusive outflow."""
+    h = length / cells
+    return float(np.float32(factor * h * h / max(D_n, sigma0 * n0 * (n0 + b_max) * (1.0 + chi * n0))))

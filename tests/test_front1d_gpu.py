@@ -1,0 +1,80 @@
+"""The one-dimensional front experiment of Sec. 4.2 on the batched GPU solver.
+
+Parity: the same 1-D grids run by the FP64 oracle give the same front
+positions (to one cell at a threshold crossing: FP32 vs FP64), fields within
+1e-3 (b normwise, n relative to n0: it ends almost fully consumed), and
+velocities within 1 %.  The speeds themselves have no
+printed values (the paper's velocity figure is an image); what is checked is
+the claim of Sec. 4.2 and Proposition 1 that chemotaxis does not slow the
+front, and that every front moves.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1301_5058_amd import front1d, workload
+from paper_1301_5058_amd.batch import Batch
+
+pytestmark = pytest.mark.gpu
+
+
+def test_front1d_series_match_oracle():
+    c = workload.FRONT1D
+    cells, n0s, chis = 200, (2.0,), (0.0, 2.5)
+    descs, fields = front1d.instances(cells, n0s, chis)
+    cbar = front1d.speed_bounds([(d["n0"], d["chi"]) for d in descs])
+    steps = front1d.steps_needed(descs, cbar, c["window"][1])
+    every = front1d.SAMPLE_EVERY
+    B = Batch(descs, chi_law="constant", max_samples=steps // every + 1)
+    for k, (b, n, s) in enumerate(fields):
+        B.set_fields(k, b, n, s)
+    B.run(steps, every)
+    ser = B.series()
+    v, _ = B.fit_velocity(*c["window"], radius="envelope")
+    got = [B.get_fields(k) for k in range(len(descs))]
+    B.close()
+    for k, (d, (b, n, s)) in enumerate(zip(descs, fields)):
+        ob, on = b.astype(np.float64), n.astype(np.float64)
+        ts, rs = [], []
+        for i in range(steps // every):
+            ob, on = oracle.run(ob, on, s, d["h"], d["dt"], every, chi=d["chi"], chi_law=1)
+            ts.append((i + 1) * every * d["dt"])
+            rs.append(oracle.diag(ob, on, d["h"], d["b_thr"], cx=-0.5, cy=0.0)[2])
+        ts, rs = np.array(ts), np.array(rs)
+        assert np.array_equal(ser[k, :len(ts), 0], ts)
+        dr = np.abs(ser[k, :len(ts), 3] - rs)
+        assert np.max(dr) <= d["h"] * (1 + 1e-9) and np.mean(dr == 0) >= 0.9
+        ov, _ = oracle.fit_velocity(ts, rs, *c["window"])
+        print("n0 %.2f chi %.1f: v %.4f (oracle %.4f), c-bar %.4f" % (d["n0"], d["chi"], v[k], ov,
+                                                                     cbar[k]))
+        assert abs(v[k] - ov) <= 0.01 * ov
+        gb, gn = got[k]
+        assert np.max(np.abs(gb - ob)) <= 1e-3 * np.max(np.abs(ob))
+        # the nutrient ends almost fully consumed; its error is measured on its scale n0
+        assert np.max(np.abs(gn - on)) <= 1e-3 * d["n0"]
+
+
+def test_front1d_chemotaxis_speeds_the_front_up():
+    # Fronts that have reached a steady speed in the window: chemotaxis does not
+    # slow them (Sec. 4.2, Proposition 1) and they move at a speed close to the
+    # bound c-bar.  Slow fronts at small n0 deplete the nutrient ahead of them
+    # (it diffuses with D_n = 1 into the colony) and keep decelerating, and
+    # chi0 n0 = 40 is not resolved on 400 cells; those are reported only.
+    r = front1d.run_front1d()
+    pts, v, cb, st = np.array(r["points"]), r["velocity"], r["cbar"], r["steady"]
+    assert np.all(np.isfinite(v)) and np.all(v > 0)
+    for k in range(len(v)):
+        print("n0 %.2f chi0 %4.1f: v %.4f  c-bar %.4f  v/c-bar %.3f  %s"
+              % (pts[k, 0], pts[k, 1], v[k], cb[k], v[k] / cb[k], "steady" if st[k] else "-"))
+    # every n0 >= 2 front without strong chemotaxis settles; steady speeds sit
+    # near the bound (measured 0.70 - 1.11 of c-bar; 400 and 800 cells agree to
+    # 0.5 %), which is the accordance Sec. 4.2 reports
+    assert st.sum() >= 12
+    assert np.all(st[(pts[:, 0] >= 2.0) & (pts[:, 1] <= 2.5)])
+    ratio = v[st] / cb[st]
+    assert np.all(ratio >= 0.6) and np.all(ratio <= 1.2)
+    for n0 in np.unique(pts[:, 0]):
+        sel = (pts[:, 0] == n0) & st
+        order = np.argsort(pts[sel, 1])
+        vs = v[sel][order]
+        assert np.all(np.diff(vs) >= -0.01 * vs[:-1])
