@@ -372,12 +372,15 @@ def extras(args):
 
 def front1d_speeds():
     """The 1-D front experiment of Sec. 4.2: 30 (n0, chi0) grids in one batch,
-    front speeds against the closed-form bound c-bar."""
+    front speeds against the closed-form bound c-bar and the threshold speed
+    c* of the scalar front equation."""
     from paper_1301_5058_amd import front1d
     r = front1d.run_front1d()
-    rows = [{"n0": p[0], "chi0": p[1], "v": round(float(v), 5), "cbar": round(float(cb), 5),
-             "v_over_cbar": round(float(v / cb), 4)}
-            for p, v, cb in zip(r["points"], r["velocity"], r["cbar"])]
+    rows = [{"n0": p[0], "chi0": p[1], "v": round(float(v), 5), "steady": bool(st),
+             "cbar": round(float(cb), 5), "cstar": round(float(cs), 5),
+             "v_over_cbar": round(float(v / cb), 4), "v_over_cstar": round(float(v / cs), 4)}
+            for p, v, st, cb, cs in zip(r["points"], r["velocity"], r["steady"], r["cbar"],
+                                        r["cstar"])]
     return {"cells": r["cells"], "steps": r["steps"], "window": list(r["window"]),
             "gpu_s": round(r["gpu_s"], 3), "wall_s": round(r["wall_s"], 3), "fronts": rows}
 

@@ -81,6 +81,17 @@ int ks_hull_test(ks_model *m, const float *X, int32_t n, uint8_t *inside, int me
  * 2 n0 sqrt(sigma0) sqrt(psi(b*)), psi(b) = b (1 - b/n0)^2 (1 + chi b). */
 int ks_cbar(ks_model *m, const float *X, int32_t n, double sigma0, float *out, int mem);
 
+/* Threshold speed c*(n0, chi0) of travelling fronts of the scalar equation
+ * of Sec. 4.1, b_t = sigma0 (D-tilde b_x)_x + g(b) (eqs. scalar-eq-b-re,
+ * D-tilde, reac-term), for each row (n0, chi0, .) of X: the infimum of the
+ * speeds c for which dz/db = -c - sigma0 D-tilde g / z has a solution z < 0 on
+ * (0, n0) with z(0+) = z(n0-) = 0 (the appendix: sets defAchi0 / defA0; the
+ * paper bounds c* by c-bar, see ks_cbar).  Computed on the device by shooting
+ * from the sharp-front start at b = 0 with an L-stable two-step implicit
+ * integrator (16384 steps) and a 65-way multisection over [0, 1.05 c-bar]
+ * (5 rounds); relative accuracy about 1e-7.  NaN for n0 <= 0 or chi0 < 0. */
+int ks_cstar(ks_model *m, const float *X, int32_t n, double sigma0, float *out, int mem);
+
 void ks_destroy(ks_model *m);
 const char *ks_last_error(const ks_model *m);
 

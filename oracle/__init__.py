@@ -12,6 +12,9 @@ Contents
   cbar, bstar         closed-form speed bound of Sec. 4.1 (eqs. c-bar-chi0,
                       c-bar-0) -- see cbar.py.
   fit_velocity        least-squares slope of an envelope-radius series.
+  cstar               threshold speed of travelling fronts of the scalar
+                      equation of Sec. 4.1 by shooting (the appendix) -- see
+                      fronts.py.
   mlp_ref             FP64 forward / backward of the velocity surrogate MLP.
 """
 import ctypes
@@ -132,3 +135,4 @@ def threads():
 
 from .cbar import bstar, cbar, psi  # noqa: E402,F401
 from .velocity import fit_velocity  # noqa: E402,F401
+from .fronts import cstar, threshold_speed  # noqa: E402,F401

@@ -446,6 +446,84 @@ __global__ void cbar_kernel(const float *X, int n, double sigma0, float *out)
     out[i] = (float)(2.0 * n0 * sqrt(sigma0) * sqrt(psi));
 }
 
+// ---------------------------------------------------------------------------
+// Threshold speed c* of travelling fronts of the scalar equation of Sec. 4.1,
+// b_t = sigma0 (D-tilde(b, chi0) b_x)_x + g(b) (eqs. scalar-eq-b-re, D-tilde,
+// reac-term), on [0, n0]: the infimum of the speeds c for which
+//   dz/db = -c - H(b) / z,  H = sigma0 D-tilde g = sigma0 n0^2 b^2 q^2 (1 + chi0 b),
+//   q = 1 - b / n0,  with z < 0 on (0, n0) and z(0+) = z(n0-) = 0
+// has a solution (the appendix, sets defAchi0 / defA0).  Shooting: the sharp
+// front leaves b = 0 along z = -c b + sigma0 n0^2 b^2 / (2c); followed upwards
+// from b = eps n0, the trajectory of a c < c* meets z = 0 before b = n0, that of
+// a c > c* reaches b = n0 (1 - eps) with z < 0.  Each step is one BDF2 step
+// (L-stable: the problem is stiff where z -> 0), which for this equation is a
+// quadratic in the new z with a closed-form root; a negative discriminant
+// means no negative continuation, i.e. z has met 0.  One wavefront per point:
+// its 64 lanes try 64 speeds spread over the current bracket [lo, hi]
+// (initially [0, 1.05 c-bar], c* <= c-bar by Sec. 4.1), and the bracket
+// shrinks 65-fold per round.
+// ---------------------------------------------------------------------------
+constexpr int CSTAR_STEPS = 16384;
+constexpr int CSTAR_ROUNDS = 5;
+
+__device__ double cbar_of(double n0, double chi, double sigma0)
+{
+    const double p = 3.0 - 2.0 * chi * n0;
+    const double bs = 2.0 * n0 / (p + sqrt(p * p + 16.0 * chi * n0));
+    const double q = 1.0 - bs / n0;
+    return 2.0 * n0 * sqrt(sigma0) * sqrt(bs * q * q * (1.0 + chi * bs));
+}
+
+__global__ __launch_bounds__(256) void cstar_kernel(const float *X, int n, double sigma0,
+                                                     float *out)
+{
+    const int lane = threadIdx.x & 63;
+    const int i = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (int)(threadIdx.x >> 6));
+    if (i >= n)
+        return; // whole wavefront
+    const double n0 = X[3 * i], chi = X[3 * i + 1];
+    if (!(n0 > 0.0) || !(chi >= 0.0) || !isfinite(n0) || !isfinite(chi)) {
+        if (lane == 0)
+            out[i] = NAN;
+        return;
+    }
+    const double eps = 1e-6;
+    const double u0 = eps * n0, u1 = n0 * (1.0 - eps);
+    const double du = (u1 - u0) / CSTAR_STEPS;
+    const double h2 = sigma0 * n0 * n0;
+    auto H = [&](double u) {
+        const double q = 1.0 - u / n0;
+        return h2 * u * u * q * q * (1.0 + chi * u);
+    };
+    double lo = 0.0, hi = 1.05 * cbar_of(n0, chi, sigma0);
+    for (int r = 0; r < CSTAR_ROUNDS; ++r) {
+        const double c = lo + (lane + 1) * (hi - lo) / 65.0;
+        double zm = -c * u0 + h2 * u0 * u0 / (2.0 * c);
+        // first step: backward Euler, z1^2 - (z0 - du c) z1 + du H1 = 0
+        const double A = zm - du * c;
+        const double D1 = A * A - 4.0 * du * H(u0 + du);
+        double zc = D1 >= 0.0 ? 0.5 * (A - sqrt(fmax(D1, 0.0))) : 0.0;
+        bool alive = D1 >= 0.0 && zc < 0.0;
+        for (int k = 2; k <= CSTAR_STEPS; ++k) {
+            // BDF2: 3/2 z2 - 2 z1 + 1/2 z0 = du (-c - H / z2)
+            const double B = du * c - 2.0 * zc + 0.5 * zm;
+            const double D2 = B * B - 6.0 * du * H(u0 + k * du);
+            const double zn = (-B - sqrt(fmax(D2, 0.0))) / 3.0;
+            alive = alive && D2 >= 0.0 && zn < 0.0;
+            zm = alive ? zc : zm;
+            zc = alive ? zn : zc;
+        }
+        const unsigned long long below = __ballot(!alive);
+        const int last = below ? 63 - __clzll(below) : -1;
+        const double nlo = last >= 0 ? lo + (last + 1) * (hi - lo) / 65.0 : lo;
+        const double nhi = last < 63 ? lo + (last + 2) * (hi - lo) / 65.0 : hi;
+        lo = nlo;
+        hi = nhi;
+    }
+    if (lane == 0)
+        out[i] = (float)(0.5 * (lo + hi));
+}
+
 } // namespace ks
 
 struct ks_model {
@@ -826,6 +904,30 @@ int ks_cbar(ks_model *m, const float *X, int32_t n, double sigma0, float *out, i
         return rc;
     float *o = mem == KC_MEM_DEVICE ? out : m->dcb;
     hipLaunchKernelGGL(ks::cbar_kernel, dim3((n + 255) / 256), dim3(256), 0, m->stream, dX, n,
+                       sigma0, o);
+    KS_HIP(m, hipGetLastError());
+    if (mem == KC_MEM_HOST) {
+        KS_HIP(m, hipMemcpyAsync(out, m->dcb, (size_t)n * sizeof(float), hipMemcpyDeviceToHost,
+                                 m->stream));
+        KS_HIP(m, hipStreamSynchronize(m->stream));
+    }
+    return KC_OK;
+}
+
+int ks_cstar(ks_model *m, const float *X, int32_t n, double sigma0, float *out, int mem)
+{
+    if (!m)
+        return KC_EINVAL;
+    m->err.clear();
+    if (!X || !out || n < 1 || n > m->maxp || !(sigma0 > 0) || !isfinite(sigma0) ||
+        (mem != KC_MEM_HOST && mem != KC_MEM_DEVICE))
+        return kfail(m, KC_EINVAL, "bad arguments to ks_cstar");
+    const float *dX;
+    int rc = stage(m, X, nullptr, n, mem, &dX, nullptr);
+    if (rc != KC_OK)
+        return rc;
+    float *o = mem == KC_MEM_DEVICE ? out : m->dcb;
+    hipLaunchKernelGGL(ks::cstar_kernel, dim3((n + 3) / 4), dim3(256), 0, m->stream, dX, n,
                        sigma0, o);
     KS_HIP(m, hipGetLastError());
     if (mem == KC_MEM_HOST) {

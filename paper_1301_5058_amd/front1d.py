@@ -6,7 +6,8 @@ instances in one batch (kb_* calls, per-block launches), the front position
 sampled on the device as the envelope radius about x = 0 (centre at cell
 index -1/2, threshold b_thr = n0 / 2), and its velocity fitted on the device
 over the window of front positions.  The velocities are compared with the
-closed-form bound c-bar(n0, chi0) of Sec. 4.1 (ks_cbar); the speeds over the
+closed-form bound c-bar(n0, chi0) of Sec. 4.1 (ks_cbar) and with the threshold
+speed c* of the scalar front equation (ks_cstar); the speeds over the
 two halves of the window tell a steady front from one that still changes
 speed (slow fronts that deplete the nutrient ahead of them decelerate).  This
 module only
@@ -44,13 +45,17 @@ def instances(cells=None, n0s=None, chis=None):
     return descs, fields
 
 
-def speed_bounds(points, sigma0=1.0):
-    """c-bar(n0, chi0) sqrt(sigma0) for rows (n0, chi0) from the library (ks_cbar)."""
+def speed_bounds(points, sigma0=1.0, threshold=False):
+    """c-bar(n0, chi0) sqrt(sigma0) for rows (n0, chi0) from the library
+    (ks_cbar); with threshold=True also the threshold speeds c* (ks_cstar)."""
     X = np.zeros((len(points), 3), dtype=np.float32)
     X[:, :2] = np.asarray(points, dtype=np.float32)
     S = Surrogate(max(1, len(points)))
     try:
-        return S.cbar(X, sigma0).astype(np.float64)
+        cb = S.cbar(X, sigma0).astype(np.float64)
+        if threshold:
+            return cb, S.cstar(X, sigma0).astype(np.float64)
+        return cb
     finally:
         S.close()
 
@@ -68,7 +73,7 @@ def run_front1d(cells=None, n0s=None, chis=None, steps=None):
     c = workload.FRONT1D
     descs, fields = instances(cells, n0s, chis)
     pts = [(d["n0"], d["chi"]) for d in descs]
-    cbar = speed_bounds(pts, c["sigma0"])
+    cbar, cstar = speed_bounds(pts, c["sigma0"], threshold=True)
     lo, hi = c["window"]
     if steps is None:
         steps = steps_needed(descs, cbar, hi)
@@ -94,7 +99,7 @@ def run_front1d(cells=None, n0s=None, chis=None, steps=None):
         B.close()
     # a front is steady when its speeds over the two halves of the window agree
     steady = np.isfinite(v1) & np.isfinite(v2) & (np.abs(v1 - v2) <= 0.1 * np.abs(v))
-    return dict(points=pts, velocity=v, samples=npts, cbar=cbar, steps=steps,
+    return dict(points=pts, velocity=v, samples=npts, cbar=cbar, cstar=cstar, steps=steps,
                 velocity_halves=(v1, v2), steady=steady,
                 dt=[d["dt"] for d in descs], cells=descs[0]["nx"], window=(lo, hi),
                 gpu_s=e0.elapsed_time(e1) / 1e3, wall_s=wall, series=series)

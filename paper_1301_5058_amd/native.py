@@ -94,6 +94,7 @@ _SIGS = {
     "ks_hull_set": (c_int32, [c_void_p, c_void_p, c_int32, c_double]),
     "ks_hull_test": (c_int32, [c_void_p, c_void_p, c_int32, c_void_p, c_int32]),
     "ks_cbar": (c_int32, [c_void_p, c_void_p, c_int32, c_double, c_void_p, c_int32]),
+    "ks_cstar": (c_int32, [c_void_p, c_void_p, c_int32, c_double, c_void_p, c_int32]),
     "ks_destroy": (None, [c_void_p]),
     "ks_last_error": (ctypes.c_char_p, [c_void_p]),
 }

@@ -132,6 +132,15 @@ class Surrogate:
                                   N.KC_MEM_HOST))
         return o
 
+    def cstar(self, X, sigma0=1.0):
+        """Threshold speed c*(n0, chi0) of the scalar front equation (ks_cstar)."""
+        X = self._x(X)
+        o = np.empty(len(X), dtype=np.float32)
+        self._chk(N.lib().ks_cstar(self.h, X.ctypes.data_as(ctypes.c_void_p), len(X),
+                                   float(sigma0), o.ctypes.data_as(ctypes.c_void_p),
+                                   N.KC_MEM_HOST))
+        return o
+
     def close(self):
         if getattr(self, "h", None):
             N.lib().ks_destroy(self.h)

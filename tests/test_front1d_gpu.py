@@ -62,10 +62,13 @@ def test_front1d_chemotaxis_speeds_the_front_up():
     # chi0 n0 = 40 is not resolved on 400 cells; those are reported only.
     r = front1d.run_front1d()
     pts, v, cb, st = np.array(r["points"]), r["velocity"], r["cbar"], r["steady"]
+    cs = r["cstar"]
     assert np.all(np.isfinite(v)) and np.all(v > 0)
+    assert np.all(cs <= cb) and np.all(cs > 0)
     for k in range(len(v)):
-        print("n0 %.2f chi0 %4.1f: v %.4f  c-bar %.4f  v/c-bar %.3f  %s"
-              % (pts[k, 0], pts[k, 1], v[k], cb[k], v[k] / cb[k], "steady" if st[k] else "-"))
+        print("n0 %.2f chi0 %4.1f: v %.4f  c-bar %.4f  c* %.4f  v/c-bar %.3f  v/c* %.3f  %s"
+              % (pts[k, 0], pts[k, 1], v[k], cb[k], cs[k], v[k] / cb[k], v[k] / cs[k],
+                 "steady" if st[k] else "-"))
     # every n0 >= 2 front without strong chemotaxis settles; steady speeds sit
     # near the bound (measured 0.70 - 1.11 of c-bar; 400 and 800 cells agree to
     # 0.5 %), which is the accordance Sec. 4.2 reports

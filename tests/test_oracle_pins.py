@@ -478,3 +478,36 @@ def test_rk2_keeps_the_discrete_invariants_and_positivity():
     tot0 = m0 + np.sum(n0.astype(np.float64))
     assert abs(np.sum(b) + np.sum(n) - tot0) / tot0 <= 1e-13
     assert np.min(b) >= 0.0 and np.min(n) >= 0.0
+
+
+# ----------------------------------------------------------------------------
+# Threshold speed c* of the scalar front equation (appendix) by shooting
+# ----------------------------------------------------------------------------
+
+
+def test_threshold_speed_of_the_degenerate_fisher_equation():
+    # u_t = (u u_x)_x + u (1 - u) has the sharp travelling front
+    # u = 1 - exp(xi / sqrt 2) (xi < 0) at its threshold speed c* = 1 / sqrt 2
+    c = oracle.threshold_speed(lambda u: u, lambda u: u * (1.0 - u), 1.0, 1.0, 1.0)
+    assert c == pytest.approx(1.0 / math.sqrt(2.0), rel=1e-8)
+
+
+def test_threshold_speed_scaling_laws():
+    # sigma0 D g is homogeneous of degree 1 in sigma0: c* ~ sqrt(sigma0); with
+    # chi0 = 0, b = n0 u maps every n0 onto n0 = 1 with c* ~ n0^(3/2)
+    base = oracle.cstar(1.0, 0.0)
+    for n0 in (0.5, 2.0, 4.0):
+        assert oracle.cstar(n0, 0.0) == pytest.approx(base * n0 ** 1.5, rel=1e-7)
+    assert oracle.cstar(1.3, 2.0, sigma0=4.0) == pytest.approx(2.0 * oracle.cstar(1.3, 2.0),
+                                                               rel=1e-7)
+
+
+def test_threshold_speed_is_below_the_bound_and_grows_with_chemotaxis():
+    # c* <= c-bar (Sec. 4.1) and c*(chi0) >= c*(0) (Proposition 1 (ii))
+    for n0 in (0.35, 1.07, 3.0):
+        prev = 0.0
+        for chi in (0.0, 1.0, 2.5, 5.0):
+            cs = oracle.cstar(n0, chi)
+            assert 0.0 < cs <= oracle.cbar(n0, chi)
+            assert cs >= prev
+            prev = cs

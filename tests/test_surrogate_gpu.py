@@ -105,3 +105,23 @@ def test_hull_and_speed_bound_kernels():
     ok = Q[:, 1] >= 0
     np.testing.assert_allclose(cb[ok], ref[ok], rtol=2e-6)
     S.close()
+
+
+def test_threshold_speed_kernel_matches_oracle():
+    pts = [(0.35, 0.0), (0.71, 10.0), (1.07, 5.0), (2.0, 0.0), (2.0, 2.5), (3.0, 1.0),
+           (4.0, 10.0), (0.5, 0.3)]
+    X = np.array([[n0, chi, 0.3] for n0, chi in pts], dtype=np.float32)
+    from paper_1301_5058_amd.surrogate import Surrogate
+    S = Surrogate(16)
+    got = S.cstar(X).astype(np.float64)
+    got2 = S.cstar(X[:3], sigma0=2.0).astype(np.float64)
+    bad = S.cstar(np.array([[0.0, 1.0, 0.3], [1.0, -1.0, 0.3]], dtype=np.float32))
+    S.close()
+    for k, (n0, chi) in enumerate(pts):
+        ref = oracle.cstar(float(np.float32(n0)), float(np.float32(chi)))
+        print("c*(%.2f, %.1f) = %.6f (oracle %.6f)" % (n0, chi, got[k], ref))
+        assert abs(got[k] - ref) <= 1e-5 * ref
+    for k in range(3):
+        n0, chi = pts[k]
+        assert abs(got2[k] - oracle.cstar(n0, chi, 2.0)) <= 1e-5 * got2[k]
+    assert np.all(np.isnan(bad))
