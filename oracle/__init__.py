@@ -9,6 +9,8 @@ Contents
                       eqs. eqnadim / eqbadim of Sec. 2.4 with no-flux
                       boundaries (eq. bconds), forward Euler or the
                       two-stage Runge-Kutta method (Sec. 3) built from it.
+  run_noise           the same steps with the agar field redrawn at every
+                      step from a counter-based generator (Philox4x32-10).
   cbar, bstar         closed-form speed bound of Sec. 4.1 (eqs. c-bar-chi0,
                       c-bar-0) -- see cbar.py.
   fit_velocity        least-squares slope of an envelope-radius series.
@@ -61,6 +63,18 @@ def _load():
         lib.oracle_run.restype = ctypes.c_int
         lib.oracle_run_rk2.argtypes = lib.oracle_run.argtypes
         lib.oracle_run_rk2.restype = ctypes.c_int
+        u32p = ctypes.POINTER(ctypes.c_uint32)
+        lib.oracle_philox4x32_10.argtypes = [u32p, u32p, u32p]
+        lib.oracle_philox4x32_10.restype = None
+        lib.oracle_noise_delta.argtypes = [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int,
+                                           ctypes.c_int]
+        lib.oracle_noise_delta.restype = ctypes.c_double
+        lib.oracle_run_noise.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                         ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                         ctypes.c_double, ctypes.c_double, ctypes.c_int, dp, dp,
+                                         ctypes.c_double, ctypes.c_double, ctypes.c_uint64,
+                                         ctypes.c_int64, ctypes.c_long, ctypes.c_int]
+        lib.oracle_run_noise.restype = ctypes.c_int
         lib.oracle_diag.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, dp, dp,
                                     ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                     dp, dp, dp, dp]
@@ -109,6 +123,35 @@ def run(b, n, sigma, h, dt, nsteps, integrator="euler", **p):
             _ptr(b), _ptr(n), _ptr(sigma), int(nsteps))
     if rc != 0:
         raise MemoryError("oracle_run: out of memory")
+    return b, n
+
+
+def philox4x32_10(counter, key):
+    """The raw Philox4x32-10 generator (4 words out of 4 counter and 2 key words)."""
+    lib = _load()
+    c = (ctypes.c_uint32 * 4)(*[int(v) & 0xffffffff for v in counter])
+    k = (ctypes.c_uint32 * 2)(*[int(v) & 0xffffffff for v in key])
+    o = (ctypes.c_uint32 * 4)()
+    lib.oracle_philox4x32_10(c, k, o)
+    return [int(v) for v in o]
+
+
+def noise_delta(seed, step, i, j):
+    """The triangular agar perturbation Delta of cell (i, j) at time step `step`."""
+    return float(_load().oracle_noise_delta(int(seed), int(step), int(i), int(j)))
+
+
+def run_noise(b, n, h, dt, nsteps, sigma0, amp, seed, step0=0, integrator="euler", **p):
+    """nsteps steps with the agar field sigma0 (1 + amp Delta) redrawn at every
+    step (steps step0, step0 + 1, ...); returns (b, n) as new float64 arrays."""
+    lib = _load()
+    b, n = _f64(b).copy(), _f64(n).copy()
+    ny, nx = b.shape
+    integ = {"euler": 0, "rk2": 1}[integrator]
+    rc = lib.oracle_run_noise(nx, ny, float(h), float(dt), *_params(p), _ptr(b), _ptr(n),
+                              float(sigma0), float(amp), int(seed), int(step0), int(nsteps), integ)
+    if rc != 0:
+        raise MemoryError("oracle_run_noise: out of memory")
     return b, n
 
 

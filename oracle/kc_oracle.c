@@ -191,6 +191,97 @@ int oracle_run_rk2(int nx, int ny, double h, double dt,
 }
 
 /*
+ * Per-step agar noise.  The paper perturbs the agar hardness at every point
+ * and every time step, sigma = sigma0 (1 + Delta) with Delta triangular on
+ * [-1, 1] (Sec. 3).  Reading: sigma = sigma0 (1 + a Delta), Delta = U1 + U2 - 1
+ * with U1, U2 uniform, drawn from the counter-based generator Philox4x32-10
+ * (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as easy as 1, 2, 3",
+ * SC 2011): counter (i / 2, j, step low word, step high word), key (seed low
+ * word, seed high word); cell i even takes output words 0, 1, i odd words 2, 3;
+ * each word keeps its top 23 bits, so Delta = (k1 + k2) 2^-23 - 1 exactly.
+ */
+static void philox4x32_10(uint32_t ctr[4], uint32_t k0, uint32_t k1)
+{
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) { /* key schedule: Weyl increments */
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const uint64_t p0 = (uint64_t)0xD2511F53u * ctr[0];
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * ctr[2];
+        const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        const uint32_t x0 = hi1 ^ ctr[1] ^ k0, x2 = hi0 ^ ctr[3] ^ k1;
+        ctr[0] = x0;
+        ctr[1] = lo1;
+        ctr[2] = x2;
+        ctr[3] = lo0;
+    }
+}
+
+/* The raw generator, for its known-answer tests. */
+void oracle_philox4x32_10(const uint32_t *ctr_in, const uint32_t *key, uint32_t *out)
+{
+    uint32_t c[4] = {ctr_in[0], ctr_in[1], ctr_in[2], ctr_in[3]};
+    philox4x32_10(c, key[0], key[1]);
+    for (int i = 0; i < 4; ++i)
+        out[i] = c[i];
+}
+
+/* Delta of cell (i, j) at time step `step` (see above). */
+double oracle_noise_delta(uint64_t seed, int64_t step, int i, int j)
+{
+    uint32_t c[4] = {(uint32_t)i >> 1, (uint32_t)j, (uint32_t)((uint64_t)step & 0xffffffffu),
+                     (uint32_t)((uint64_t)step >> 32)};
+    philox4x32_10(c, (uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32));
+    const uint32_t w1 = (i & 1) ? c[2] : c[0], w2 = (i & 1) ? c[3] : c[1];
+    const double u = (double)((w1 >> 9) + (w2 >> 9)); /* integer < 2^24 */
+    return u * (1.0 / 8388608.0) - 1.0;                /* 2^-23 */
+}
+
+/* sigma of every cell at time step `step`. */
+static void noise_sigma(int nx, int ny, double sigma0, double amp, uint64_t seed, int64_t step,
+                        double *sg)
+{
+#pragma omp parallel for schedule(static)
+    for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i)
+            sg[(long)j * nx + i] = sigma0 * (1.0 + amp * oracle_noise_delta(seed, step, i, j));
+}
+
+/*
+ * nsteps steps with a fresh agar field at every step (steps step0,
+ * step0 + 1, ...): forward Euler (integrator 0) or the two-stage Runge-Kutta
+ * step (1), whose two stages share the step's field.  Returns 0, or -5.
+ */
+int oracle_run_noise(int nx, int ny, double h, double dt,
+                     double D_n, double theta, double kappa, double chi, int chi_law,
+                     double *b, double *n, double sigma0, double amp, uint64_t seed,
+                     int64_t step0, long nsteps, int integrator)
+{
+    const size_t cells = (size_t)nx * (size_t)ny;
+    double *buf = (double *)malloc(7 * cells * sizeof(double));
+    if (!buf)
+        return -5;
+    double *sg = buf, *b1 = buf + cells, *n1 = buf + 2 * cells, *b2 = buf + 3 * cells;
+    double *n2 = buf + 4 * cells, *bn = buf + 5 * cells, *nn = buf + 6 * cells;
+    for (long s = 0; s < nsteps; ++s) {
+        noise_sigma(nx, ny, sigma0, amp, seed, step0 + s, sg);
+        if (integrator == 0)
+            oracle_step(nx, ny, h, dt, D_n, theta, kappa, chi, chi_law, b, n, sg, bn, nn);
+        else
+            oracle_rk2_step(nx, ny, h, dt, D_n, theta, kappa, chi, chi_law, b, n, sg, b1, n1,
+                            b2, n2, bn, nn);
+        for (size_t p = 0; p < cells; ++p) {
+            b[p] = bn[p];
+            n[p] = nn[p];
+        }
+    }
+    free(buf);
+    return 0;
+}
+
+/*
  * Diagnostics of one level:
  *   mass     = h^2 * sum b     (summed in row order)
  *   nutrient = h^2 * sum n

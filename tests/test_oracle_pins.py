@@ -511,3 +511,59 @@ def test_threshold_speed_is_below_the_bound_and_grows_with_chemotaxis():
             assert 0.0 < cs <= oracle.cbar(n0, chi)
             assert cs >= prev
             prev = cs
+
+
+# ----------------------------------------------------------------------------
+# Per-step agar noise (Sec. 3): sigma = sigma0 (1 + a Delta), Delta triangular
+# ----------------------------------------------------------------------------
+def test_philox_known_answer_vectors():
+    rows = _golden("philox4x32_10_kat.txt")
+    assert len(rows) == 3
+    for ctr, key, out in rows:
+        c = [int(w, 16) for w in ctr.split()]
+        k = [int(w, 16) for w in key.split()]
+        o = [int(w, 16) for w in out.split()]
+        assert oracle.philox4x32_10(c, k) == o
+
+
+def test_noise_delta_is_triangular_on_the_23_bit_grid():
+    seed, n = 12345, 60000
+    d = np.array([oracle.noise_delta(seed, s, i, j) for s, i, j in
+                  zip(np.arange(n) % 7, np.arange(n) % 300, np.arange(n) // 300)])
+    assert np.all(d >= -1.0) and np.all(d < 1.0)
+    assert np.all((d + 1.0) * 2.0 ** 23 == np.round((d + 1.0) * 2.0 ** 23))
+    assert abs(np.mean(d)) <= 4.0 * math.sqrt(1.0 / 6.0 / n)
+    assert abs(np.var(d) - 1.0 / 6.0) <= 0.01
+    # the triangular law: P(|Delta| <= x) = 1 - (1 - x)^2
+    for x in (0.1, 0.3, 0.5, 0.8):
+        assert abs(np.mean(np.abs(d) <= x) - (1.0 - (1.0 - x) ** 2)) <= 0.01
+
+
+def test_noise_layout_pairs_cells_on_one_generator_call():
+    seed, step, j = (7 << 32) | 11, (3 << 32) | 5, 9
+    for q in (0, 4):
+        w = oracle.philox4x32_10([q, j, step & 0xffffffff, step >> 32], [seed & 0xffffffff,
+                                                                        seed >> 32])
+        for i, (a, b) in ((2 * q, (w[0], w[1])), (2 * q + 1, (w[2], w[3]))):
+            assert oracle.noise_delta(seed, step, i, j) == ((a >> 9) + (b >> 9)) / 2.0 ** 23 - 1.0
+
+
+def test_noise_runs_reduce_to_the_static_field_and_keep_the_invariants():
+    b0, n0, s = _small_fields()
+    dt = workload.config_dt(b0, n0, s, factor=0.1)
+    ones = np.full_like(s, 1.5)
+    # amplitude 0: the static field sigma0 everywhere, bit for bit
+    rb, rn = oracle.run(b0, n0, ones, 1.0, dt, 50, chi=0.5)
+    nb, nn = oracle.run_noise(b0, n0, 1.0, dt, 50, 1.5, 0.0, 99, chi=0.5)
+    assert np.array_equal(rb, nb) and np.array_equal(rn, nn)
+    # with noise the fluxes still telescope: sum b is conserved without growth
+    nb, nn = oracle.run_noise(b0, n0, 1.0, dt, 300, 1.0, 0.5, 99, theta=0.0, chi=0.5)
+    m0 = np.sum(b0.astype(np.float64))
+    assert abs(np.sum(nb) - m0) / m0 <= 1e-13 and np.min(nb) >= 0.0
+    # a run in two pieces (step0) equals one run; another seed differs
+    a1, a2 = oracle.run_noise(b0, n0, 1.0, dt, 40, 1.0, 0.5, 99, chi=0.5)
+    p1, p2 = oracle.run_noise(b0, n0, 1.0, dt, 15, 1.0, 0.5, 99, chi=0.5)
+    p1, p2 = oracle.run_noise(p1, p2, 1.0, dt, 25, 1.0, 0.5, 99, step0=15, chi=0.5)
+    assert np.array_equal(a1, p1) and np.array_equal(a2, p2)
+    o1, _ = oracle.run_noise(b0, n0, 1.0, dt, 40, 1.0, 0.5, 100, chi=0.5)
+    assert not np.array_equal(a1, o1)
