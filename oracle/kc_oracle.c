@@ -196,9 +196,10 @@ int oracle_run_rk2(int nx, int ny, double h, double dt,
  * [-1, 1] (Sec. 3).  Reading: sigma = sigma0 (1 + a Delta), Delta = U1 + U2 - 1
  * with U1, U2 uniform, drawn from the counter-based generator Philox4x32-10
  * (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as easy as 1, 2, 3",
- * SC 2011): counter (i / 2, j, step low word, step high word), key (seed low
- * word, seed high word); cell i even takes output words 0, 1, i odd words 2, 3;
- * each word keeps its top 23 bits, so Delta = (k1 + k2) 2^-23 - 1 exactly.
+ * SC 2011): counter (i / 4, j, step low word, step high word), key (seed low
+ * word, seed high word); cell i takes output word i mod 4, whose two 16-bit
+ * halves k1, k2 give Delta = (k1 + k2) 2^-16 - 1 exactly (one generator call
+ * serves four neighbouring cells).
  */
 static void philox4x32_10(uint32_t ctr[4], uint32_t k0, uint32_t k1)
 {
@@ -231,12 +232,12 @@ void oracle_philox4x32_10(const uint32_t *ctr_in, const uint32_t *key, uint32_t 
 /* Delta of cell (i, j) at time step `step` (see above). */
 double oracle_noise_delta(uint64_t seed, int64_t step, int i, int j)
 {
-    uint32_t c[4] = {(uint32_t)i >> 1, (uint32_t)j, (uint32_t)((uint64_t)step & 0xffffffffu),
+    uint32_t c[4] = {(uint32_t)i >> 2, (uint32_t)j, (uint32_t)((uint64_t)step & 0xffffffffu),
                      (uint32_t)((uint64_t)step >> 32)};
     philox4x32_10(c, (uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32));
-    const uint32_t w1 = (i & 1) ? c[2] : c[0], w2 = (i & 1) ? c[3] : c[1];
-    const double u = (double)((w1 >> 9) + (w2 >> 9)); /* integer < 2^24 */
-    return u * (1.0 / 8388608.0) - 1.0;                /* 2^-23 */
+    const uint32_t w = c[i & 3];
+    const double u = (double)((w & 0xffffu) + (w >> 16)); /* integer < 2^17 */
+    return u * (1.0 / 65536.0) - 1.0;                     /* 2^-16 */
 }
 
 /* sigma of every cell at time step `step`. */

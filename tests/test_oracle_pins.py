@@ -526,12 +526,12 @@ def test_philox_known_answer_vectors():
         assert oracle.philox4x32_10(c, k) == o
 
 
-def test_noise_delta_is_triangular_on_the_23_bit_grid():
+def test_noise_delta_is_triangular_on_the_16_bit_grid():
     seed, n = 12345, 60000
     d = np.array([oracle.noise_delta(seed, s, i, j) for s, i, j in
                   zip(np.arange(n) % 7, np.arange(n) % 300, np.arange(n) // 300)])
     assert np.all(d >= -1.0) and np.all(d < 1.0)
-    assert np.all((d + 1.0) * 2.0 ** 23 == np.round((d + 1.0) * 2.0 ** 23))
+    assert np.all((d + 1.0) * 2.0 ** 16 == np.round((d + 1.0) * 2.0 ** 16))
     assert abs(np.mean(d)) <= 4.0 * math.sqrt(1.0 / 6.0 / n)
     assert abs(np.var(d) - 1.0 / 6.0) <= 0.01
     # the triangular law: P(|Delta| <= x) = 1 - (1 - x)^2
@@ -539,13 +539,14 @@ def test_noise_delta_is_triangular_on_the_23_bit_grid():
         assert abs(np.mean(np.abs(d) <= x) - (1.0 - (1.0 - x) ** 2)) <= 0.01
 
 
-def test_noise_layout_pairs_cells_on_one_generator_call():
+def test_noise_layout_serves_four_cells_from_one_generator_call():
     seed, step, j = (7 << 32) | 11, (3 << 32) | 5, 9
     for q in (0, 4):
         w = oracle.philox4x32_10([q, j, step & 0xffffffff, step >> 32], [seed & 0xffffffff,
                                                                         seed >> 32])
-        for i, (a, b) in ((2 * q, (w[0], w[1])), (2 * q + 1, (w[2], w[3]))):
-            assert oracle.noise_delta(seed, step, i, j) == ((a >> 9) + (b >> 9)) / 2.0 ** 23 - 1.0
+        for r in range(4):
+            half = (w[r] & 0xffff) + (w[r] >> 16)
+            assert oracle.noise_delta(seed, step, 4 * q + r, j) == half / 2.0 ** 16 - 1.0
 
 
 def test_noise_runs_reduce_to_the_static_field_and_keep_the_invariants():
