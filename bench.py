@@ -13,8 +13,8 @@ that tracks the colony envelope does.  Inputs are resident in HBM before the
 timed region.  Prints one JSON line.
 
 The line also carries, under "extras", the other workloads of the solver:
-the FP64 variant, chi = 0 and the two-stage Runge-Kutta integrator (FP32 and
-FP64) at 4096^2, the 16384^2 grid (20,000 steps), the 256-instance batched
+the FP64 variant, chi = 0, the two-stage Runge-Kutta integrator (FP32 and
+FP64) and the per-step agar noise at 4096^2, the 16384^2 grid (20,000 steps), the 256-instance batched
 sweep (30,000 steps), the velocity map (surrogate with solver fallback) and
 the 1-D front-speed experiment of Sec. 4.2.  --no-extras skips them.
 """
@@ -42,6 +42,8 @@ OPS_PER_CELL_UPDATE = 33
 # of b and n
 OPS_PER_RK2_UPDATE = 2 * OPS_PER_CELL_UPDATE + 4
 BYTES_PER_CELL_LAUNCH = {"fp32": 20, "fp64": 40}  # read b, n, sigma; write b', n'
+# per-step agar noise of the 4096^2 workload: sigma = 1 + 0.5 Delta, redrawn every step
+NOISE_4096 = {"sigma0": 1.0, "amp": 0.5, "seed": 2013}
 SAMPLE_EVERY = 100
 T_START = time.perf_counter()
 METRIC = "GCell-updates/s & % HBM peak (4096^2 FP32); velocity-map pts/s at <=2% err"
@@ -242,9 +244,11 @@ def run(args):
     return out
 
 
-def single_variant(nx, n0, a, chi, precision, steps, tune_effort=0, integrator="euler"):
+def single_variant(nx, n0, a, chi, precision, steps, tune_effort=0, integrator="euler",
+                   noise=None):
     """GCell-updates/s of one single-instance configuration (autotuned); with
-    integrator="rk2" an update is one two-stage Runge-Kutta step."""
+    integrator="rk2" an update is one two-stage Runge-Kutta step, with noise
+    (dict sigma0, amp, seed) the agar field is redrawn at every step."""
     import numpy as np
     import torch
     from paper_1301_5058_amd import workload
@@ -255,8 +259,11 @@ def single_variant(nx, n0, a, chi, precision, steps, tune_effort=0, integrator="
         b, n, s = (x.astype(np.float64) for x in (b, n, s))
     stream = torch.cuda.current_stream()
     S = Solver(nx, nx, dt=dt, chi=chi, precision=precision, b_thr=0.5 * n0, stream=stream,
-               integrator=integrator)
-    S.set_fields(*(torch.from_numpy(x).cuda() for x in (b, n, s)))
+               integrator=integrator, noise=noise)
+    if noise is None:
+        S.set_fields(*(torch.from_numpy(x).cuda() for x in (b, n, s)))
+    else:
+        S.set_fields(*(torch.from_numpy(x).cuda() for x in (b, n)))
     S.autotune(effort=tune_effort, use_cache=True)
     T, rows, pf = S.tuning()
     S.step(100)
@@ -266,7 +273,8 @@ def single_variant(nx, n0, a, chi, precision, steps, tune_effort=0, integrator="
     rl, _ = roofline(precision, nx * nx, T, lm, ops)
     S.close()
     return {"gcell_s": round(nx * nx * steps / (ms / 1e3) / 1e9, 2), "steps": steps,
-            "integrator": integrator, "tsteps": T, "rows": rows, "prefetch": pf,
+            "integrator": integrator, "noise": noise is not None, "tsteps": T, "rows": rows,
+            "prefetch": pf,
             "launch_us": round(lm * 1e3, 2), "roofline_bound": rl["bound"],
             "roofline_frac": rl["frac"]}
 
@@ -359,6 +367,10 @@ def extras(args):
     progress("rk2 4096^2: %s" % ex["rk2_4096_fp32"])
     ex["rk2_4096_fp64"] = single_variant(4096, 0.5, 0.5, 1.0, "fp64", 4000, integrator="rk2")
     progress("rk2 fp64 4096^2: %s" % ex["rk2_4096_fp64"])
+    # the paper's agar noise: sigma redrawn at every cell and step (Philox4x32-10)
+    ex["noise_4096_fp32"] = single_variant(4096, 0.5, 0.5, 1.0, "fp32", 20000,
+                                           noise=NOISE_4096)
+    progress("noise 4096^2: %s" % ex["noise_4096_fp32"])
     ex["hires_16384"] = hires(20000)
     progress("16384^2: %s" % ex["hires_16384"])
     ex["sweep_256"] = sweep()

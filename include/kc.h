@@ -64,6 +64,17 @@ enum { KC_MEM_HOST = 0, KC_MEM_DEVICE = 1 };
  * in strong-stability-preserving form: with E one forward-Euler step,
  * u' = (u + E(E(u))) / 2.  Both have the same stability bound. */
 enum { KC_EULER = 0, KC_RK2 = 1 };
+/* Agar field.  KC_NOISE_STATIC: the sigma field given to kc_set_fields, fixed
+ * for the run.  KC_NOISE_PER_STEP: the paper's hardness perturbed at every
+ * point and time step (Sec. 3), sigma = sigma0 (1 + noise_amp Delta) with Delta
+ * triangular on [-1, 1], drawn from the counter-based generator Philox4x32-10
+ * (Salmon, Moraes, Dror, Shaw, SC 2011): counter (x / 4, y, step low word,
+ * step high word), key (noise_seed low word, high word); cell x takes output
+ * word x mod 4, whose 16-bit halves k1, k2 give Delta = (k1 + k2) 2^-16 - 1.
+ * `step` is the global step count (step0 + steps taken); the two stages of a
+ * KC_RK2 step share the step's field.  Fields are the same for any kernel
+ * configuration and any split of a run into kc_step calls. */
+enum { KC_NOISE_STATIC = 0, KC_NOISE_PER_STEP = 1 };
 
 typedef struct kc_ctx kc_ctx;
 
@@ -83,11 +94,15 @@ typedef struct {
     double cx, cy;     /* envelope centre in cell-index units (default (nx-1)/2, (ny-1)/2) */
     int64_t step0;     /* step count at which the given fields sit (time = steps * dt)     */
     int32_t integrator; /* KC_EULER or KC_RK2                                              */
+    int32_t noise;      /* KC_NOISE_STATIC or KC_NOISE_PER_STEP                            */
+    double sigma0;      /* per-step noise: mean hardness sigma0 > 0                        */
+    double noise_amp;   /* per-step noise: amplitude a, 0 <= a < 1 (sigma stays > 0)       */
+    uint64_t noise_seed; /* per-step noise: generator key                                  */
 } kc_params;
 
 /* Fill *p with the normalised defaults: D_n = theta = kappa = 1, chi = 0,
  * receptor law, FP32, b_thr = 0.5, centre unset (NaN -> grid centre), step0 = 0,
- * forward Euler. */
+ * forward Euler, static agar field (sigma0 = 1, noise_amp = 0, seed 0). */
 void kc_default_params(kc_params *p);
 
 /* Create a context for grid g, cell width h > 0 and time step dt > 0 on the
@@ -100,7 +115,9 @@ int kc_create(const kc_grid *g, double h, double dt, const kc_params *p, void *h
  * eq. CoefCrsDif) into the context; mem says where the three arrays live.
  * Rejects NaN / Inf / negative entries (KC_ENONFINITE) and a dt above the
  * explicit stability bound for these fields (KC_EUNSTABLE); on failure the
- * context keeps its previous state.  Resets the step count to p->step0. */
+ * context keeps its previous state.  Resets the step count to p->step0.
+ * With KC_NOISE_PER_STEP sigma is not used (may be NULL) and the bound takes
+ * the largest sigma the noise can draw, sigma0 (1 + noise_amp). */
 int kc_set_fields(kc_ctx *ctx, const void *b0, const void *n0, const void *sigma, int mem);
 
 /* Advance nsteps >= 0 forward-Euler steps (enqueued, asynchronous). */

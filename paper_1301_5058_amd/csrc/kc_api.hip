@@ -86,15 +86,21 @@ int check_params(const kc_params *p)
         return KC_EINVAL;
     if (p->integrator != KC_EULER && p->integrator != KC_RK2)
         return KC_EINVAL;
+    if (p->noise != KC_NOISE_STATIC && p->noise != KC_NOISE_PER_STEP)
+        return KC_EINVAL;
+    if (p->noise == KC_NOISE_PER_STEP &&
+        (!(p->sigma0 > 0) || !isfinite(p->sigma0) || !(p->noise_amp >= 0) || !(p->noise_amp < 1)))
+        return KC_EINVAL;
     return KC_OK;
 }
 
 // Default wavefront-strip height: the fewest whole rounds of the wavefronts the
 // device holds at once with strips of at most 128 rows.
-int default_rows(int precision, int chi_law, int integrator, const kc::Tuning &t, int nx, int ny)
+int default_rows(int precision, int chi_law, int integrator, bool noise, const kc::Tuning &t,
+                 int nx, int ny)
 {
     // no half-empty last round; long strips amortise the warm-up rows at either end
-    const int w = kc::resident_waves(precision, chi_law, integrator, t.tsteps, t.prefetch);
+    const int w = kc::resident_waves(precision, chi_law, integrator, t.tsteps, t.prefetch, noise);
     const int levels = kc::stream_levels(integrator, t.tsteps);
     for (int q = 1; q <= 64 && w > 0; ++q) {
         const int r = kc::round_fitted_rows(precision, levels, nx, ny, w, q);
@@ -120,6 +126,19 @@ template <typename R> Coef<R> make_coef(const kc_ctx *c)
     k.upt = (R)(c->dt * c->p.kappa);
     k.chi2 = (R)(2.0 * c->p.chi);
     return k;
+}
+
+// Per-step noise parameters for a launch starting at the context's current step.
+template <typename R> kc::Noise<R> make_noise(const kc_ctx *c)
+{
+    kc::Noise<R> z;
+    z.sigma0 = (R)c->p.sigma0;
+    z.amp = (R)c->p.noise_amp;
+    z.k0 = (uint32_t)(c->p.noise_seed & 0xffffffffu);
+    z.k1 = (uint32_t)(c->p.noise_seed >> 32);
+    z.s_lo = (uint32_t)((uint64_t)c->steps & 0xffffffffu);
+    z.s_hi = (uint32_t)((uint64_t)c->steps >> 32);
+    return z;
 }
 
 template <typename R> Fields<R> make_fields(const kc_ctx *c)
@@ -153,8 +172,11 @@ template <typename R> int step_impl(kc_ctx *c, int64_t nsteps)
         if (e != hipSuccess)
             return hipfail(c, e, "stage-1 level allocation");
     }
+    const bool noise = c->p.noise == KC_NOISE_PER_STEP;
     while (nsteps > 0) {
         const Fields<R> f = make_fields<R>(c);
+        const kc::Noise<R> z = make_noise<R>(c);
+        const kc::Noise<R> *zp = noise ? &z : nullptr;
         hipError_t e;
         int adv;
         if (c->ref && integ == KC_RK2) {
@@ -162,21 +184,21 @@ template <typename R> int step_impl(kc_ctx *c, int64_t nsteps)
             Fields<R> f1 = f;
             f1.b_out = (R *)c->b1;
             f1.n_out = (R *)c->n1;
-            e = kc::launch_ref<R>(f1, k, c->p.chi_law, c->stream);
+            e = kc::launch_ref<R>(f1, k, c->p.chi_law, c->stream, nullptr, nullptr, zp);
             Fields<R> f2 = f;
             f2.b_in = (const R *)c->b1;
             f2.n_in = (const R *)c->n1;
             if (e == hipSuccess)
-                e = kc::launch_ref<R>(f2, k, c->p.chi_law, c->stream, f.b_in, f.n_in);
+                e = kc::launch_ref<R>(f2, k, c->p.chi_law, c->stream, f.b_in, f.n_in, zp);
             adv = 1;
         } else if (c->ref) {
-            e = kc::launch_ref<R>(f, k, c->p.chi_law, c->stream);
+            e = kc::launch_ref<R>(f, k, c->p.chi_law, c->stream, nullptr, nullptr, zp);
             adv = 1;
         } else {
             kc::Tuning t = c->tune;
             const int64_t want = nsteps < t.tsteps ? nsteps : t.tsteps;
             t.tsteps = kc::stream_depth_at_most((int)want, integ);
-            e = kc::launch_stream<R>(f, k, c->p.chi_law, integ, t, c->stream);
+            e = kc::launch_stream<R>(f, k, c->p.chi_law, integ, t, c->stream, zp);
             adv = t.tsteps;
         }
         if (e != hipSuccess)
@@ -217,8 +239,11 @@ template <typename R> int autotune_impl(kc_ctx *c, int effort, double *best_out)
     const Fields<R> f = make_fields<R>(c); // current level in, scratch level out
     kc::Tuning cand[256];
     int n = 0;
-    kc::tuning_candidates(effort, c->p.precision, c->p.chi_law, c->p.integrator, c->nx, c->ny,
-                          cand, &n, 256);
+    const bool noise = c->p.noise == KC_NOISE_PER_STEP;
+    const kc::Noise<R> z = make_noise<R>(c);
+    const kc::Noise<R> *zp = noise ? &z : nullptr;
+    kc::tuning_candidates(effort, c->p.precision, c->p.chi_law, c->p.integrator, noise, c->nx,
+                          c->ny, cand, &n, 256);
     const double cells = (double)c->nx * c->ny;
     // pass 1: every candidate once; pass 2: the six fastest again, twice each
     // with longer runs, keeping each one's best (single timings are noisy)
@@ -229,7 +254,8 @@ template <typename R> int autotune_impl(kc_ctx *c, int effort, double *best_out)
         reps = reps < 3 ? 3 : reps > 30 ? 30 : reps;
         double ms = 0;
         hipError_t e =
-            kc::time_stream<R>(f, k, c->p.chi_law, c->p.integrator, cand[i], c->stream, reps, &ms);
+            kc::time_stream<R>(f, k, c->p.chi_law, c->p.integrator, cand[i], c->stream, reps, &ms,
+                               zp);
         if (e != hipSuccess)
             return hipfail(c, e, "autotune launch");
         order.push_back(std::make_pair(ms / cand[i].tsteps, i));
@@ -245,7 +271,8 @@ template <typename R> int autotune_impl(kc_ctx *c, int effort, double *best_out)
             reps = reps < 6 ? 6 : reps > 90 ? 90 : reps;
             double ms = 0;
             hipError_t e =
-                kc::time_stream<R>(f, k, c->p.chi_law, c->p.integrator, t, c->stream, reps, &ms);
+                kc::time_stream<R>(f, k, c->p.chi_law, c->p.integrator, t, c->stream, reps, &ms,
+                                   zp);
             if (e != hipSuccess)
                 return hipfail(c, e, "autotune launch");
             if (ms / t.tsteps < best) {
@@ -277,6 +304,10 @@ void kc_default_params(kc_params *p)
     p->cy = NAN;
     p->step0 = 0;
     p->integrator = KC_EULER;
+    p->noise = KC_NOISE_STATIC;
+    p->sigma0 = 1.0;
+    p->noise_amp = 0.0;
+    p->noise_seed = 0;
 }
 
 const char *kc_strerror(int s)
@@ -348,7 +379,8 @@ int kc_create(const kc_grid *g, double h, double dt, const kc_params *p, void *h
     // can change it)
     c->tune.tsteps = p->integrator == KC_RK2 ? 2 : 4;
     c->tune.prefetch = 4;
-    c->tune.rows = default_rows(p->precision, p->chi_law, p->integrator, c->tune, c->nx, c->ny);
+    c->tune.rows = default_rows(p->precision, p->chi_law, p->integrator,
+                                p->noise == KC_NOISE_PER_STEP, c->tune, c->nx, c->ny);
 
     int rc = KC_OK;
     hipError_t e = hipGetDevice(&c->device);
@@ -417,16 +449,45 @@ int kc_set_fields(kc_ctx *c, const void *b0, const void *n0, const void *sigma, 
     if (!c)
         return KC_EINVAL;
     c->err.clear();
-    if (!b0 || !n0 || !sigma)
+    const bool noise = c->p.noise == KC_NOISE_PER_STEP;
+    if (!b0 || !n0 || (!sigma && !noise))
         return fail(c, KC_EINVAL, "null field pointer");
     if (mem != KC_MEM_HOST && mem != KC_MEM_DEVICE)
         return fail(c, KC_EINVAL, "bad memory kind %d", mem);
     const size_t cells = (size_t)c->nx * c->ny;
+    // with per-step noise the check sees sigma = 1 and the stability bound is
+    // scaled by the largest sigma the noise can draw, sigma0 (1 + amp)
+    std::vector<unsigned char> ones;
+    void *dones = nullptr;
+    if (noise) {
+        ones.resize(cells * c->esz);
+        for (size_t i = 0; i < cells; ++i) {
+            if (c->esz == 4) {
+                const float v = 1.0f;
+                memcpy(&ones[i * 4], &v, 4);
+            } else {
+                const double v = 1.0;
+                memcpy(&ones[i * 8], &v, 8);
+            }
+        }
+        sigma = ones.data();
+        if (mem == KC_MEM_DEVICE) {
+            KC_HIP(c, hipMalloc(&dones, cells * c->esz));
+            const hipError_t e =
+                hipMemcpy(dones, ones.data(), cells * c->esz, hipMemcpyHostToDevice);
+            if (e != hipSuccess) {
+                (void)hipFree(dones);
+                return hipfail(c, e, "noise check staging");
+            }
+            sigma = dones;
+        }
+    }
     double mx = 0.0;
+    int rc = KC_OK;
     if (mem == KC_MEM_HOST) {
-        const int rc = kc_check_fields(c->nx, c->ny, c->p.precision, b0, n0, sigma, &mx);
+        rc = kc_check_fields(c->nx, c->ny, c->p.precision, b0, n0, sigma, &mx);
         if (rc != KC_OK)
-            return fail(c, rc, "input fields rejected: %s", kc_strerror(rc));
+            rc = fail(c, rc, "input fields rejected: %s", kc_strerror(rc));
     } else {
         const int cp = kc::check_parts(cells);
         hipError_t e = c->p.precision == KC_FP32
@@ -436,21 +497,31 @@ int kc_set_fields(kc_ctx *c, const void *b0, const void *n0, const void *sigma, 
                            : kc::launch_check<double>((const double *)b0, (const double *)n0,
                                                       (const double *)sigma, cells, c->dparts,
                                                       c->stream);
-        if (e != hipSuccess)
-            return hipfail(c, e, "input check kernel");
-        KC_HIP(c, hipMemcpyAsync(c->hout, c->dparts, 2 * cp * sizeof(double),
-                                 hipMemcpyDeviceToHost, c->stream));
-        KC_HIP(c, hipStreamSynchronize(c->stream));
-        double nbad = 0.0;
-        for (int i = 0; i < cp; ++i) {
-            nbad += c->hout[2 * i];
-            if (c->hout[2 * i + 1] > mx)
-                mx = c->hout[2 * i + 1];
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(c->hout, c->dparts, 2 * cp * sizeof(double),
+                               hipMemcpyDeviceToHost, c->stream);
+        if (e == hipSuccess)
+            e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) {
+            rc = hipfail(c, e, "input check kernel");
+        } else {
+            double nbad = 0.0;
+            for (int i = 0; i < cp; ++i) {
+                nbad += c->hout[2 * i];
+                if (c->hout[2 * i + 1] > mx)
+                    mx = c->hout[2 * i + 1];
+            }
+            if (nbad > 0)
+                rc = fail(c, KC_ENONFINITE, "input fields rejected: %.0f NaN/Inf/negative entries",
+                          nbad);
         }
-        if (nbad > 0)
-            return fail(c, KC_ENONFINITE, "input fields rejected: %.0f NaN/Inf/negative entries",
-                        nbad);
     }
+    if (dones)
+        (void)hipFree(dones);
+    if (rc != KC_OK)
+        return rc;
+    if (noise)
+        mx *= c->p.sigma0 * (1.0 + c->p.noise_amp);
     const double dmax = c->p.D_n > mx ? c->p.D_n : mx;
     if (dmax > 0 && c->dt > c->h * c->h / (4.0 * dmax))
         return fail(c, KC_EUNSTABLE, "dt = %g exceeds h^2/(4 max(D_n, sigma n b)) = %g", c->dt,
@@ -461,7 +532,8 @@ int kc_set_fields(kc_ctx *c, const void *b0, const void *n0, const void *sigma, 
     c->cur = 0;
     KC_HIP(c, hipMemcpy2DAsync(c->b[0], dpitch, b0, spitch, spitch, c->ny, kind, c->stream));
     KC_HIP(c, hipMemcpy2DAsync(c->n[0], dpitch, n0, spitch, spitch, c->ny, kind, c->stream));
-    KC_HIP(c, hipMemcpy2DAsync(c->sg, dpitch, sigma, spitch, spitch, c->ny, kind, c->stream));
+    if (!noise)
+        KC_HIP(c, hipMemcpy2DAsync(c->sg, dpitch, sigma, spitch, spitch, c->ny, kind, c->stream));
     KC_HIP(c, hipStreamSynchronize(c->stream));
     c->has_fields = true;
     c->steps = c->p.step0;
@@ -592,7 +664,7 @@ int kc_autotune(kc_ctx *c, int32_t effort, int32_t use_cache, double *gcell_s)
         return fail(c, KC_ESTATE, "kc_autotune before kc_set_fields");
     char key[256];
     kc::device_key(key, sizeof key, c->nx, c->ny, c->p.precision, c->p.chi_law,
-                   c->p.integrator);
+                   c->p.integrator, c->p.noise == KC_NOISE_PER_STEP);
     if (gcell_s)
         *gcell_s = 0.0;
     kc::Tuning t;

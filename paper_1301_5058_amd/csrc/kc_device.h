@@ -94,6 +94,88 @@ template <typename R> __device__ __forceinline__ R rk2_average(R u, R e2)
 }
 
 // ---------------------------------------------------------------------------
+// Per-step agar noise (Sec. 3): sigma = sigma0 (1 + a Delta), Delta triangular
+// on [-1, 1], redrawn for every cell and time step from the counter-based
+// generator Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random
+// numbers: as easy as 1, 2, 3", SC 2011).  Counter (x / 4, y, step low word,
+// step high word), key (seed low word, seed high word); cell x takes output
+// word x mod 4, and its two 16-bit halves k1, k2 give Delta = (k1 + k2) 2^-16
+// - 1, exact in either precision.
+// ---------------------------------------------------------------------------
+template <typename R> struct Noise {
+    R sigma0, amp;
+    uint32_t k0, k1;    // seed words
+    uint32_t s_lo, s_hi; // time step of the launch's first step
+};
+
+__device__ __forceinline__ void philox4x32_10(uint32_t &c0, uint32_t &c1, uint32_t &c2,
+                                              uint32_t &c3, uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t x0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        const uint32_t x2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)p1;
+        c3 = (uint32_t)p0;
+        c0 = x0;
+        c2 = x2;
+        k0 += 0x9E3779B9u; // Weyl key schedule
+        k1 += 0xBB67AE85u;
+    }
+}
+
+// Step `ds` after the launch's first step, as (low, high) words.
+template <typename R>
+__device__ __forceinline__ void noise_step(const Noise<R> &z, int ds, uint32_t &lo, uint32_t &hi)
+{
+    lo = z.s_lo + (uint32_t)ds;
+    hi = z.s_hi + (lo < z.s_lo ? 1u : 0u);
+}
+
+// sigma of one generator word.
+template <typename R> __device__ __forceinline__ R noise_sigma(const Noise<R> &z, uint32_t w)
+{
+    const R delta = (R)((w & 0xffffu) + (w >> 16)) * R(1.0 / 65536.0) - R(1);
+    return z.sigma0 * (R(1) + z.amp * delta);
+}
+
+// sigma / 2 of cells x4 .. x4 + VEC - 1 of row y at step ds (x4 a multiple of VEC;
+// VEC = 4: one generator call, VEC = 2: the matching half of one).
+template <typename R, int VEC>
+__device__ __forceinline__ void noise_half_sigma(const Noise<R> &z, int ds, int x4, int y, R *out)
+{
+    uint32_t lo, hi;
+    noise_step<R>(z, ds, lo, hi);
+    uint32_t c0 = (uint32_t)x4 >> 2, c1 = (uint32_t)y, c2 = lo, c3 = hi;
+    philox4x32_10(c0, c1, c2, c3, z.k0, z.k1);
+    if (VEC == 4) { // x4 is a multiple of 4: the whole call
+        out[0] = R(0.5) * noise_sigma<R>(z, c0);
+        out[1] = R(0.5) * noise_sigma<R>(z, c1);
+        out[2 % VEC] = R(0.5) * noise_sigma<R>(z, c2);
+        out[3 % VEC] = R(0.5) * noise_sigma<R>(z, c3);
+    } else { // VEC = 2: words 0, 1 or 2, 3
+        const bool upper = (x4 & 2) != 0;
+        out[0] = R(0.5) * noise_sigma<R>(z, upper ? c2 : c0);
+        out[1 % VEC] = R(0.5) * noise_sigma<R>(z, upper ? c3 : c1);
+    }
+}
+
+// sigma / 2 of the single cell (x, y) at step ds (the reference kernel).
+template <typename R>
+__device__ __forceinline__ R noise_half_sigma1(const Noise<R> &z, int ds, int x, int y)
+{
+    uint32_t lo, hi;
+    noise_step<R>(z, ds, lo, hi);
+    uint32_t c0 = (uint32_t)x >> 2, c1 = (uint32_t)y, c2 = lo, c3 = hi;
+    philox4x32_10(c0, c1, c2, c3, z.k0, z.k1);
+    const int q = x & 3;
+    const uint32_t w = q == 0 ? c0 : q == 1 ? c1 : q == 2 ? c2 : c3;
+    return R(0.5) * noise_sigma<R>(z, w);
+}
+
+// ---------------------------------------------------------------------------
 // Cross-lane moves inside a 64-lane wavefront (DPP wave shifts, GFX9 family).
 //   from_next(v): lane i receives lane i+1's v (lane 63 receives 0)
 //   from_prev(v): lane i receives lane i-1's v (lane 0 receives 0)

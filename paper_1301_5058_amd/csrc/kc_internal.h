@@ -40,27 +40,33 @@ struct StreamGeom {
 };
 StreamGeom stream_geom(int precision, int levels, int nx, int ny, int rows);
 
-// One launch advancing t.tsteps steps of `integrator` with the fused kernel.
+// One launch advancing t.tsteps steps of `integrator` with the fused kernel;
+// with z non-null the agar field is redrawn at every step (z's step words are
+// the launch's first step) and f.sg is not read.
 template <typename R>
 hipError_t launch_stream(const Fields<R> &f, const Coef<R> &c, int chi_law, int integrator,
-                         const Tuning &t, hipStream_t s);
+                         const Tuning &t, hipStream_t s, const Noise<R> *z = nullptr);
 // One forward-Euler step with the global-memory reference kernel; with b_avg
-// non-null the result is averaged with (b_avg, n_avg) (Runge-Kutta stage 2).
+// non-null the result is averaged with (b_avg, n_avg) (Runge-Kutta stage 2);
+// with z non-null sigma is drawn for z's step.
 template <typename R>
 hipError_t launch_ref(const Fields<R> &f, const Coef<R> &c, int chi_law, hipStream_t s,
-                      const R *b_avg = nullptr, const R *n_avg = nullptr);
+                      const R *b_avg = nullptr, const R *n_avg = nullptr,
+                      const Noise<R> *z = nullptr);
 
 // Average duration (ms) of one fused launch with tuning t, from `reps` launches
 // after one warm-up launch, timed with HIP events on stream s.  The launch
 // reads f's input level and writes its output level; nothing else changes.
 template <typename R>
 hipError_t time_stream(const Fields<R> &f, const Coef<R> &c, int chi_law, int integrator,
-                       const Tuning &t, hipStream_t s, int reps, double *ms);
+                       const Tuning &t, hipStream_t s, int reps, double *ms,
+                       const Noise<R> *z = nullptr);
 
 // Wavefronts of the fused kernel (precision, law, integrator, depth, prefetch)
 // that the device holds at once: blocks per compute unit x 4 x compute units
 // (0 on error).
-int resident_waves(int precision, int chi_law, int integrator, int tsteps, int prefetch);
+int resident_waves(int precision, int chi_law, int integrator, int tsteps, int prefetch,
+                   bool noise = false);
 // Rows per strip such that the strips of a launch of `levels` levels fill at
 // most `rounds` rounds of `waves` resident wavefronts (0 when none does).
 int round_fitted_rows(int precision, int levels, int nx, int ny, int waves, int rounds);
@@ -69,14 +75,15 @@ int round_fitted_rows(int precision, int levels, int nx, int ny, int waves, int 
 // full grid (tsteps in {1,2,3,4,6,8}, at most 3 for Runge-Kutta, rows in
 // 8..256, prefetch 2 or 4); both add, per depth, the rows that fill 1..8 whole
 // rounds of resident wavefronts.
-void tuning_candidates(int effort, int precision, int chi_law, int integrator, int nx, int ny,
-                       Tuning *out, int *n, int cap);
+void tuning_candidates(int effort, int precision, int chi_law, int integrator, bool noise,
+                       int nx, int ny, Tuning *out, int *n, int cap);
 
 // Autotune cache: one JSON object per line, keyed by device, grid, precision,
 // sensitivity law and (for Runge-Kutta) integrator.  Path from KC_AUTOTUNE_CACHE, else none.
 bool cache_lookup(const char *key, int integrator, Tuning *t);
 void cache_store(const char *key, const Tuning &t, double gcells);
-int device_key(char *buf, size_t n, int nx, int ny, int precision, int chi_law, int integrator);
+int device_key(char *buf, size_t n, int nx, int ny, int precision, int chi_law, int integrator,
+               bool noise = false);
 
 // Diagnostics: partial sums over row blocks (4 doubles each), then one
 // fixed-order final pass writing {t, mass, nutrient, envelope radius, area

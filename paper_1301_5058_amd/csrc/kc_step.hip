@@ -17,7 +17,7 @@ namespace kc {
 // ---------------------------------------------------------------------------
 // Reference kernel
 // ---------------------------------------------------------------------------
-template <typename R, int LAW>
+template <typename R, int LAW, bool NOISE>
 __device__ __forceinline__ void ref_cell(const StepArgs<R> &a, int x, int y, R &b, R &n, R &D, R &X)
 {
     if (x < 0 || x >= a.nx || y < 0 || y >= a.ny) {
@@ -27,11 +27,11 @@ __device__ __forceinline__ void ref_cell(const StepArgs<R> &a, int x, int y, R &
     const size_t p = (size_t)y * a.pitch + x;
     b = a.b_in[p];
     n = a.n_in[p];
-    const R sh = R(0.5) * a.sg[p];
+    const R sh = NOISE ? noise_half_sigma1<R>(a.z, 0, x, y) : R(0.5) * a.sg[p];
     coef<R, LAW>(sh, n, b, a.c.chi2, D, X);
 }
 
-template <typename R, int LAW, bool AVG>
+template <typename R, int LAW, bool AVG, bool NOISE>
 __global__ __launch_bounds__(256) void step_ref(StepArgs<R> a)
 {
     const int x = blockIdx.x * 64 + (threadIdx.x & 63);
@@ -39,11 +39,11 @@ __global__ __launch_bounds__(256) void step_ref(StepArgs<R> a)
     if (x >= a.nx || y >= a.ny)
         return;
     R bP, nP, DP, XP, bE, nE, DE, XE, bW, nW, DW, XW, bN, nN, DN, XN, bS, nS, DS, XS;
-    ref_cell<R, LAW>(a, x, y, bP, nP, DP, XP);
-    ref_cell<R, LAW>(a, x + 1, y, bE, nE, DE, XE);
-    ref_cell<R, LAW>(a, x - 1, y, bW, nW, DW, XW);
-    ref_cell<R, LAW>(a, x, y + 1, bN, nN, DN, XN);
-    ref_cell<R, LAW>(a, x, y - 1, bS, nS, DS, XS);
+    ref_cell<R, LAW, NOISE>(a, x, y, bP, nP, DP, XP);
+    ref_cell<R, LAW, NOISE>(a, x + 1, y, bE, nE, DE, XE);
+    ref_cell<R, LAW, NOISE>(a, x - 1, y, bW, nW, DW, XW);
+    ref_cell<R, LAW, NOISE>(a, x, y + 1, bN, nN, DN, XN);
+    ref_cell<R, LAW, NOISE>(a, x, y - 1, bS, nS, DS, XS);
     R geb, gen, gwb, gwn, gnb, gnn, gsb, gsn;
     face<R>(bP, nP, DP, XP, bE, nE, DE, XE, x + 1 < a.nx, geb, gen);
     face<R>(bW, nW, DW, XW, bP, nP, DP, XP, x - 1 >= 0, gwb, gwn);
@@ -109,6 +109,7 @@ static StepArgs<R> make_args(const Fields<R> &f, const Coef<R> &c)
     a.b_out = f.b_out;
     a.n_out = f.n_out;
     a.b_avg = a.n_avg = nullptr;
+    a.z = Noise<R>{R(1), R(0), 0u, 0u, 0u, 0u};
     a.nx = f.nx;
     a.ny = f.ny;
     a.pitch = f.pitch;
@@ -119,24 +120,29 @@ static StepArgs<R> make_args(const Fields<R> &f, const Coef<R> &c)
 }
 
 template <typename R>
-static const void *stream_kernel(int chi_law, int integrator, int levels, int pf)
+static const void *stream_kernel(int chi_law, int integrator, bool noise, int levels, int pf)
 {
     if ((pf != 2 && pf != 4) || (integrator != 0 && integrator != 1) ||
         (chi_law != 0 && chi_law != 1))
         return nullptr;
-    return integrator == 0 ? stream_kernel_for<R, false>(chi_law, levels, pf)
-                           : stream_kernel_for<R, true>(chi_law, levels, pf);
+    if (noise)
+        return integrator == 0 ? stream_kernel_for<R, false, true>(chi_law, levels, pf)
+                               : stream_kernel_for<R, true, true>(chi_law, levels, pf);
+    return integrator == 0 ? stream_kernel_for<R, false, false>(chi_law, levels, pf)
+                           : stream_kernel_for<R, true, false>(chi_law, levels, pf);
 }
 
 template <typename R>
 hipError_t launch_stream(const Fields<R> &f, const Coef<R> &c, int chi_law, int integrator,
-                         const Tuning &t, hipStream_t s)
+                         const Tuning &t, hipStream_t s, const Noise<R> *z)
 {
     const int levels = stream_levels(integrator, t.tsteps);
-    const void *fn = stream_kernel<R>(chi_law, integrator, levels, t.prefetch);
+    const void *fn = stream_kernel<R>(chi_law, integrator, z != nullptr, levels, t.prefetch);
     if (!fn || t.rows < 1)
         return hipErrorInvalidValue;
     StepArgs<R> a = make_args(f, c);
+    if (z)
+        a.z = *z;
     const StreamGeom g = stream_geom(sizeof(R) == 4 ? 0 : 1, levels, f.nx, f.ny, t.rows);
     a.rows = t.rows;
     a.nsx = g.nsx;
@@ -146,32 +152,43 @@ hipError_t launch_stream(const Fields<R> &f, const Coef<R> &c, int chi_law, int 
     return hipLaunchKernel(fn, dim3(g.nblocks_padded), dim3(256), args, 0, s);
 }
 
+template <typename R, bool AVG, bool NOISE>
+static void launch_ref_k(int chi_law, dim3 grid, hipStream_t s, const StepArgs<R> &a)
+{
+    if (chi_law == 0)
+        hipLaunchKernelGGL((step_ref<R, 0, AVG, NOISE>), grid, dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL((step_ref<R, 1, AVG, NOISE>), grid, dim3(256), 0, s, a);
+}
+
 template <typename R>
 hipError_t launch_ref(const Fields<R> &f, const Coef<R> &c, int chi_law, hipStream_t s,
-                      const R *b_avg, const R *n_avg)
+                      const R *b_avg, const R *n_avg, const Noise<R> *z)
 {
     StepArgs<R> a = make_args(f, c);
     a.b_avg = b_avg;
     a.n_avg = n_avg;
+    if (z)
+        a.z = *z;
     const dim3 grid((f.nx + 63) / 64, (f.ny + 3) / 4);
     const bool avg = b_avg != nullptr;
-    if (chi_law == 0) {
+    if (z) {
         if (avg)
-            hipLaunchKernelGGL((step_ref<R, 0, true>), grid, dim3(256), 0, s, a);
+            launch_ref_k<R, true, true>(chi_law, grid, s, a);
         else
-            hipLaunchKernelGGL((step_ref<R, 0, false>), grid, dim3(256), 0, s, a);
+            launch_ref_k<R, false, true>(chi_law, grid, s, a);
     } else {
         if (avg)
-            hipLaunchKernelGGL((step_ref<R, 1, true>), grid, dim3(256), 0, s, a);
+            launch_ref_k<R, true, false>(chi_law, grid, s, a);
         else
-            hipLaunchKernelGGL((step_ref<R, 1, false>), grid, dim3(256), 0, s, a);
+            launch_ref_k<R, false, false>(chi_law, grid, s, a);
     }
     return hipGetLastError();
 }
 
 template <typename R>
 hipError_t time_stream(const Fields<R> &f, const Coef<R> &c, int chi_law, int integrator,
-                       const Tuning &t, hipStream_t s, int reps, double *ms)
+                       const Tuning &t, hipStream_t s, int reps, double *ms, const Noise<R> *z)
 {
     hipEvent_t e0, e1;
     hipError_t e = hipEventCreate(&e0);
@@ -182,11 +199,11 @@ hipError_t time_stream(const Fields<R> &f, const Coef<R> &c, int chi_law, int in
         (void)hipEventDestroy(e0);
         return e;
     }
-    e = launch_stream<R>(f, c, chi_law, integrator, t, s);
+    e = launch_stream<R>(f, c, chi_law, integrator, t, s, z);
     if (e == hipSuccess)
         e = hipEventRecord(e0, s);
     for (int i = 0; i < reps && e == hipSuccess; ++i)
-        e = launch_stream<R>(f, c, chi_law, integrator, t, s);
+        e = launch_stream<R>(f, c, chi_law, integrator, t, s, z);
     if (e == hipSuccess)
         e = hipEventRecord(e1, s);
     if (e == hipSuccess)
@@ -201,15 +218,17 @@ hipError_t time_stream(const Fields<R> &f, const Coef<R> &c, int chi_law, int in
     return e;
 }
 
-int resident_waves(int precision, int chi_law, int integrator, int tsteps, int prefetch)
+int resident_waves(int precision, int chi_law, int integrator, int tsteps, int prefetch,
+                   bool noise)
 {
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         return 0;
     const int levels = stream_levels(integrator, tsteps);
-    const void *fn = precision == 0 ? stream_kernel<float>(chi_law, integrator, levels, prefetch)
-                                    : stream_kernel<double>(chi_law, integrator, levels, prefetch);
+    const void *fn = precision == 0
+                         ? stream_kernel<float>(chi_law, integrator, noise, levels, prefetch)
+                         : stream_kernel<double>(chi_law, integrator, noise, levels, prefetch);
     int nb = 0;
     if (!fn || hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, 256, 0) != hipSuccess)
         return 0;
@@ -227,8 +246,8 @@ int round_fitted_rows(int precision, int levels, int nx, int ny, int waves, int 
     return (int)((ny + m - 1) / m);
 }
 
-void tuning_candidates(int effort, int precision, int chi_law, int integrator, int nx, int ny,
-                       Tuning *out, int *n, int cap)
+void tuning_candidates(int effort, int precision, int chi_law, int integrator, bool noise,
+                       int nx, int ny, Tuning *out, int *n, int cap)
 {
     static const int quick_t[] = {1, 2, 3, 4};
     static const int quick_r[] = {16, 32, 64, 128};
@@ -260,7 +279,7 @@ void tuning_candidates(int effort, int precision, int chi_law, int integrator, i
             // rows that fill a whole number of rounds of resident wavefronts
             if (nx <= 0 || ny <= 0)
                 continue;
-            const int w = resident_waves(precision, chi_law, integrator, ts[i], pf);
+            const int w = resident_waves(precision, chi_law, integrator, ts[i], pf, noise);
             for (int q = 1; q <= 8; ++q) {
                 const int r = round_fitted_rows(precision, stream_levels(integrator, ts[i]), nx,
                                                 ny, w, q);
@@ -273,16 +292,19 @@ void tuning_candidates(int effort, int precision, int chi_law, int integrator, i
 }
 
 template hipError_t time_stream<float>(const Fields<float> &, const Coef<float> &, int, int,
-                                       const Tuning &, hipStream_t, int, double *);
+                                       const Tuning &, hipStream_t, int, double *,
+                                       const Noise<float> *);
 template hipError_t time_stream<double>(const Fields<double> &, const Coef<double> &, int, int,
-                                        const Tuning &, hipStream_t, int, double *);
+                                        const Tuning &, hipStream_t, int, double *,
+                                        const Noise<double> *);
 template hipError_t launch_stream<float>(const Fields<float> &, const Coef<float> &, int, int,
-                                         const Tuning &, hipStream_t);
+                                         const Tuning &, hipStream_t, const Noise<float> *);
 template hipError_t launch_stream<double>(const Fields<double> &, const Coef<double> &, int, int,
-                                          const Tuning &, hipStream_t);
+                                          const Tuning &, hipStream_t, const Noise<double> *);
 template hipError_t launch_ref<float>(const Fields<float> &, const Coef<float> &, int, hipStream_t,
-                                      const float *, const float *);
+                                      const float *, const float *, const Noise<float> *);
 template hipError_t launch_ref<double>(const Fields<double> &, const Coef<double> &, int,
-                                       hipStream_t, const double *, const double *);
+                                       hipStream_t, const double *, const double *,
+                                       const Noise<double> *);
 
 } // namespace kc

@@ -12,6 +12,7 @@ template <typename R> struct StepArgs {
     const R *b_in, *n_in, *sg;
     R *b_out, *n_out;
     const R *b_avg, *n_avg; // step_ref with AVG: the level averaged with
+    Noise<R> z;             // per-step agar noise (NOISE kernels)
     int nx, ny, pitch;
     int rows;           // output rows per strip
     int nsx, nstrips;   // strips along x, total strips
@@ -22,7 +23,7 @@ template <typename R> struct StepArgs {
 // ---------------------------------------------------------------------------
 // Fused kernel
 // ---------------------------------------------------------------------------
-template <typename R, int T, int LAW, int PF, bool RK>
+template <typename R, int T, int LAW, int PF, bool RK, bool NOISE>
 __global__ __launch_bounds__(256) void step_stream(StepArgs<R> a)
 {
     const int lb = xcd_block(a.nblocks_padded);
@@ -42,17 +43,20 @@ __global__ __launch_bounds__(256) void step_stream(StepArgs<R> a)
     sa.pitch = a.pitch;
     sa.rows = a.rows;
     sa.c = a.c;
+    sa.z = a.z;
     sa.b_thr = sa.cx = sa.cy = 0.0;
     const int sx = strip % a.nsx, sy = strip / a.nsx;
     if (strip_interior<R, T>(sa, sx, sy))
-        stream_strip<R, T, LAW, PF, false, RK>(sa, sx, sy);
+        stream_strip<R, T, LAW, PF, false, RK, NOISE>(sa, sx, sy);
     else
-        stream_strip<R, T, LAW, PF, true, RK>(sa, sx, sy);
+        stream_strip<R, T, LAW, PF, true, RK, NOISE>(sa, sx, sy);
 }
 
-// The compiled fused kernel of precision R and integrator RK for (law, levels,
-// prefetch), or null when there is none.  Each (R, RK) pair is defined in a
-// translation unit of its own (kc_stream_<precision>_<integrator>.hip).
-template <typename R, bool RK> const void *stream_kernel_for(int chi_law, int levels, int pf);
+// The compiled fused kernel of precision R, integrator RK and noise mode NOISE
+// for (law, levels, prefetch), or null when there is none.  Each (R, RK,
+// NOISE) triple is defined in a translation unit of its own
+// (kc_stream_<precision>_<integrator>[_noise].hip).
+template <typename R, bool RK, bool NOISE>
+const void *stream_kernel_for(int chi_law, int levels, int pf);
 
 } // namespace kc

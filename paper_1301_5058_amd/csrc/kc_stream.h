@@ -11,6 +11,11 @@
 // launch: read b, n, sigma once, write b', n' once, plus halo re-reads that
 // mostly hit L2.
 //
+// With NOISE the agar field is redrawn at every time step (noise_half_sigma,
+// kc_device.h): each level computes sigma of its incoming row for the step it
+// advances instead of loading it (the two Runge-Kutta levels of a step share
+// the step's field, passed along as before).
+//
 // With RK, each time step is two levels of the two-stage Runge-Kutta method
 // u' = (u + E(E(u))) / 2 (E = one forward-Euler step): an even level hands the
 // u of its centre row to the next level together with its Euler output, and
@@ -57,6 +62,7 @@ template <typename R> struct StripArgs {
     int nx, ny, pitch;
     int rows; // output rows per strip
     Coef<R> c;
+    Noise<R> z;           // per-step agar noise (NOISE only; sg unused then)
     double b_thr, cx, cy; // envelope diagnostics (strip_diag only)
 };
 
@@ -81,7 +87,7 @@ __device__ __forceinline__ bool strip_interior(const StripArgs<R> &a, int sx, in
     return xl >= 0 && xl + WC <= a.nx - 1 && y0 >= T && y1 + T <= a.ny;
 }
 
-template <typename R, int T, int LAW, int PF, bool CHECK, bool RK = false>
+template <typename R, int T, int LAW, int PF, bool CHECK, bool RK = false, bool NOISE = false>
 __device__ __forceinline__ void stream_strip(const StripArgs<R> &a, int sx, int sy)
 {
     static_assert(!RK || T % 2 == 0, "a two-stage Runge-Kutta block has an even level count");
@@ -128,8 +134,13 @@ __device__ __forceinline__ void stream_strip(const StripArgs<R> &a, int sx, int 
         const size_t p = (size_t)min(row, last_row) * a.pitch + xc;
         vb = *reinterpret_cast<const vec_t *>(a.b_in + p);
         vn = *reinterpret_cast<const vec_t *>(a.n_in + p);
-        vs = *reinterpret_cast<const vec_t *>(a.sg + p);
+        if constexpr (!NOISE)
+            vs = *reinterpret_cast<const vec_t *>(a.sg + p);
+        else
+            vs = vec_t{};
     };
+    // time step (after the launch's first) that level L advances
+    auto level_step = [](int L) { return RK ? L / 2 : L; };
 #pragma unroll
     for (int u = 0; u < PF; ++u)
         load_row(rs + u, pb[u], pn[u], ps[u]);
@@ -151,6 +162,8 @@ __device__ __forceinline__ void stream_strip(const StripArgs<R> &a, int sx, int 
                 is[k] = R(0.5) * ps[u][k];
                 iub[k] = iun[k] = R(0);
             }
+            if (NOISE) // sigma of the incoming row at the first level's step
+                noise_half_sigma<R, VEC>(a.z, level_step(0), x0, row, is);
             load_row(row + PF, pb[u], pn[u], ps[u]);
 #pragma unroll
             for (int k = 0; k < VEC; ++k)
@@ -233,6 +246,10 @@ __device__ __forceinline__ void stream_strip(const StripArgs<R> &a, int sx, int 
                     cs[L][k] = is[k];
                 }
                 if (L + 1 < T) {
+                    if (NOISE && level_step(L + 1) != level_step(L)) {
+                        // the next level advances a later step: fresh sigma of row y
+                        noise_half_sigma<R, VEC>(a.z, level_step(L + 1), x0, y, os);
+                    }
 #pragma unroll
                     for (int k = 0; k < VEC; ++k) {
                         ib[k] = ob[k];

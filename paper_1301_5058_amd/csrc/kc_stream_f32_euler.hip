@@ -1,6 +1,6 @@
-// kc_stream_f32_euler.hip -- instantiates the fused step kernel for FP32 fields and forward Euler
-// (one translation unit per precision and integrator, so they compile in
-// parallel).
+// kc_stream_f32_euler.hip -- instantiates the fused step kernel for FP32 fields, forward Euler
+// (one translation unit per precision, integrator and noise mode, so they
+// compile in parallel).
 #include "kc_step_kernels.h"
 
 namespace kc {
@@ -9,8 +9,8 @@ namespace {
 
 template <int T, int LAW> const void *pick_pf(int pf)
 {
-    return pf == 4 ? reinterpret_cast<const void *>(&step_stream<float, T, LAW, 4, false>)
-                   : reinterpret_cast<const void *>(&step_stream<float, T, LAW, 2, false>);
+    return pf == 4 ? reinterpret_cast<const void *>(&step_stream<float, T, LAW, 4, false, false>)
+                   : reinterpret_cast<const void *>(&step_stream<float, T, LAW, 2, false, false>);
 }
 
 template <int LAW> const void *pick_levels(int levels, int pf)
@@ -28,7 +28,8 @@ template <int LAW> const void *pick_levels(int levels, int pf)
 
 } // namespace
 
-template <> const void *stream_kernel_for<float, false>(int chi_law, int levels, int pf)
+template <>
+const void *stream_kernel_for<float, false, false>(int chi_law, int levels, int pf)
 {
     return chi_law == 0 ? pick_levels<0>(levels, pf) : pick_levels<1>(levels, pf);
 }

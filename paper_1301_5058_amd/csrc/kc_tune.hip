@@ -14,7 +14,8 @@
 
 namespace kc {
 
-int device_key(char *buf, size_t n, int nx, int ny, int precision, int chi_law, int integrator)
+int device_key(char *buf, size_t n, int nx, int ny, int precision, int chi_law, int integrator,
+               bool noise)
 {
     int dev = 0;
     hipDeviceProp_t prop;
@@ -26,9 +27,11 @@ int device_key(char *buf, size_t n, int nx, int ny, int precision, int chi_law, 
     for (char *p = a; *p; ++p)
         if (*p == '"' || *p == '|' || *p == ' ')
             *p = '_';
-    // forward-Euler keys carry no integrator field; Runge-Kutta keys end in "|rk2"
-    return snprintf(buf, n, "%s|%dx%d|%s|%s%s", a, nx, ny, precision == 0 ? "fp32" : "fp64",
-                    chi_law == 0 ? "receptor" : "constant", integrator == 0 ? "" : "|rk2");
+    // forward-Euler keys carry no integrator field; Runge-Kutta keys add "|rk2",
+    // per-step noise "|noise"
+    return snprintf(buf, n, "%s|%dx%d|%s|%s%s%s", a, nx, ny, precision == 0 ? "fp32" : "fp64",
+                    chi_law == 0 ? "receptor" : "constant", integrator == 0 ? "" : "|rk2",
+                    noise ? "|noise" : "");
 }
 
 static const char *cache_path() { return getenv("KC_AUTOTUNE_CACHE"); }

@@ -16,6 +16,7 @@ KC_FP32, KC_FP64 = 0, 1
 KC_CHI_RECEPTOR, KC_CHI_CONSTANT = 0, 1
 KC_MEM_HOST, KC_MEM_DEVICE = 0, 1
 KC_EULER, KC_RK2 = 0, 1
+KC_NOISE_STATIC, KC_NOISE_PER_STEP = 0, 1
 
 c_int32, c_int64, c_double, c_void_p = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
 P_double = ctypes.POINTER(c_double)
@@ -28,7 +29,9 @@ class KcGrid(ctypes.Structure):
 class KcParams(ctypes.Structure):
     _fields_ = [("D_n", c_double), ("theta", c_double), ("kappa", c_double), ("chi", c_double),
                 ("chi_law", c_int32), ("precision", c_int32), ("b_thr", c_double),
-                ("cx", c_double), ("cy", c_double), ("step0", c_int64), ("integrator", c_int32)]
+                ("cx", c_double), ("cy", c_double), ("step0", c_int64), ("integrator", c_int32),
+                ("noise", c_int32), ("sigma0", c_double), ("noise_amp", c_double),
+                ("noise_seed", ctypes.c_uint64)]
 
 
 class KbInstance(ctypes.Structure):

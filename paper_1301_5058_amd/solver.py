@@ -24,7 +24,7 @@ def _torch_dtype(precision):
 class Solver:
     def __init__(self, nx, ny, h=1.0, dt=0.2, chi=0.0, chi_law="receptor", precision="fp32",
                  D_n=1.0, theta=1.0, kappa=1.0, b_thr=0.5, cx=None, cy=None, step0=0,
-                 stream=None, integrator="euler"):
+                 stream=None, integrator="euler", noise=None):
         self.nx, self.ny, self.h, self.dt = int(nx), int(ny), float(h), float(dt)
         p = N.default_params()
         p.D_n, p.theta, p.kappa, p.chi = float(D_n), float(theta), float(kappa), float(chi)
@@ -37,6 +37,13 @@ class Solver:
         if integrator not in ("euler", "rk2"):
             raise ValueError("integrator must be 'euler' or 'rk2'")
         p.integrator = N.KC_EULER if integrator == "euler" else N.KC_RK2
+        if noise is not None:
+            # per-step agar noise: dict(sigma0=..., amp=..., seed=...)
+            p.noise = N.KC_NOISE_PER_STEP
+            p.sigma0 = float(noise.get("sigma0", 1.0))
+            p.noise_amp = float(noise["amp"])
+            p.noise_seed = int(noise.get("seed", 0))
+        self.noise = noise
         self.precision = p.precision
         if stream is None:
             stream = torch.cuda.current_stream()
@@ -63,8 +70,13 @@ class Solver:
             raise ValueError("field must have shape (%d, %d)" % (self.ny, self.nx))
         return ctypes.c_void_p(a.ctypes.data), N.KC_MEM_HOST, a
 
-    def set_fields(self, b, n, sigma):
-        (pb, mb, kb), (pn, mn, kn), (ps, ms, ks) = self._arg(b), self._arg(n), self._arg(sigma)
+    def set_fields(self, b, n, sigma=None):
+        """sigma may be None with per-step noise (the library draws it)."""
+        (pb, mb, kb), (pn, mn, kn) = self._arg(b), self._arg(n)
+        if sigma is None:
+            ps, ms = ctypes.c_void_p(None), mb
+        else:
+            ps, ms, ks = self._arg(sigma)
         if not (mb == mn == ms):
             raise ValueError("b, n and sigma must all be host arrays or all device tensors")
         N.check(N.lib().kc_set_fields(self.ctx, pb, pn, ps, mb), self.ctx)

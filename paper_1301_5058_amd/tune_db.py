@@ -24,7 +24,9 @@ GRIDS = [  # (nx, n0, a, chi, precision, integrator)
     (4096, 0.5, 0.5, 1.0, "fp32", "euler"), (4096, 0.5, 0.5, 1.0, "fp64", "euler"),
     (16384, 0.35, 0.5, 2.0, "fp32", "euler"),
     (4096, 0.5, 0.5, 1.0, "fp32", "rk2"), (4096, 0.5, 0.5, 1.0, "fp64", "rk2"),
+    (4096, 0.5, 0.5, 1.0, "fp32", "euler+noise"),
 ]
+NOISE = {"sigma0": 1.0, "amp": 0.5, "seed": 2013}
 
 
 def main():
@@ -38,8 +40,10 @@ def main():
         dt = workload.config_dt(b, n, s)
         if prec == "fp64":
             b, n, s = (x.astype(np.float64) for x in (b, n, s))
-        S = Solver(nx, nx, dt=dt, chi=chi, precision=prec, integrator=integ)
-        S.set_fields(*(torch.from_numpy(x).cuda() for x in (b, n, s)))
+        noise = NOISE if integ.endswith("+noise") else None
+        S = Solver(nx, nx, dt=dt, chi=chi, precision=prec, integrator=integ.split("+")[0],
+                   noise=noise)
+        S.set_fields(*(torch.from_numpy(x).cuda() for x in ((b, n) if noise else (b, n, s))))
         g = S.autotune(effort=a.effort, use_cache=True)
         print("%5d^2 %s %s: tsteps=%d rows=%d prefetch=%d  %.1f GCell/s"
               % ((nx, prec, integ) + S.tuning() + (g,)), flush=True)
