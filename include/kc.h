@@ -96,7 +96,7 @@ typedef struct {
     int32_t integrator; /* KC_EULER or KC_RK2                                              */
     int32_t noise;      /* KC_NOISE_STATIC or KC_NOISE_PER_STEP                            */
     double sigma0;      /* per-step noise: mean hardness sigma0 > 0                        */
-    double noise_amp;   /* per-step noise: amplitude a, 0 <= a < 1 (sigma stays > 0)       */
+    double noise_amp;   /* per-step noise: amplitude a, 0 <= a <= 1 (a = 1: the paper's)   */
     uint64_t noise_seed; /* per-step noise: generator key                                  */
 } kc_params;
 

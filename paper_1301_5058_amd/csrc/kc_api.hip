@@ -89,7 +89,7 @@ int check_params(const kc_params *p)
     if (p->noise != KC_NOISE_STATIC && p->noise != KC_NOISE_PER_STEP)
         return KC_EINVAL;
     if (p->noise == KC_NOISE_PER_STEP &&
-        (!(p->sigma0 > 0) || !isfinite(p->sigma0) || !(p->noise_amp >= 0) || !(p->noise_amp < 1)))
+        (!(p->sigma0 > 0) || !isfinite(p->sigma0) || !(p->noise_amp >= 0) || !(p->noise_amp <= 1)))
         return KC_EINVAL;
     return KC_OK;
 }

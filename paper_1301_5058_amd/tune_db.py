@@ -1,6 +1,6 @@
 """Write the autotune database of the fused step kernel for a set of grids.
 
-    python -m paper_1301_5058_amd.tune_db OUT.jsonl [--effort 1]
+    python -m paper_1301_5058_amd.tune_db OUT.jsonl [--effort 1] [--only 2048/fp32/rk2+noise]
 
 For every (grid, precision) below, a solver is created on the workload's
 fields and kc_autotune times the candidate configurations; the winners are
@@ -25,6 +25,7 @@ GRIDS = [  # (nx, n0, a, chi, precision, integrator)
     (16384, 0.35, 0.5, 2.0, "fp32", "euler"),
     (4096, 0.5, 0.5, 1.0, "fp32", "rk2"), (4096, 0.5, 0.5, 1.0, "fp64", "rk2"),
     (4096, 0.5, 0.5, 1.0, "fp32", "euler+noise"),
+    (2048, 0.71, 0.5, 5.0, "fp32", "rk2+noise"),  # the paper's own runs
 ]
 NOISE = {"sigma0": 1.0, "amp": 0.5, "seed": 2013}
 
@@ -33,9 +34,14 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("out")
     ap.add_argument("--effort", type=int, default=1)
+    ap.add_argument("--only", default=None,
+                    help="comma-separated NX/PRECISION/INTEGRATOR entries, e.g. 2048/fp32/rk2+noise")
     a = ap.parse_args()
+    only = None if a.only is None else set(a.only.split(","))
     os.environ["KC_AUTOTUNE_CACHE"] = os.path.abspath(a.out)
     for nx, n0, amp, chi, prec, integ in GRIDS:
+        if only is not None and "%d/%s/%s" % (nx, prec, integ) not in only:
+            continue
         b, n, s = workload.fields(nx, nx, n0, amp, 0)
         dt = workload.config_dt(b, n, s)
         if prec == "fp64":

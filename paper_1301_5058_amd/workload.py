@@ -121,3 +121,55 @@ def front1d_dt(cells, length, n0, chi=0.0, b_max=0.71, sigma0=1.0, D_n=1.0, fact
     bound of the donor-cell step counts next to the diffusive outflow."""
     h = length / cells
     return float(np.float32(factor * h * h / max(D_n, sigma0 * n0 * (n0 + b_max) * (1.0 + chi * n0))))
+
+
+# ---------------------------------------------------------------------------
+# The paper's two-dimensional runs (Sec. 3, Table tabresparam): a square of
+# side L = 680 with N = 2048 cells per side, inoculum b_M exp(-(x^2+y^2)/6.25)
+# (b_M = 0.71) about the centre of the square, uniform nutrient n0, and
+# sigma = sigma0 (1 + Delta) redrawn at every cell and step (noise amplitude
+# 1), integrated with the two-stage Runge-Kutta method.  Each figure set
+# compares two sensitivities chi0 at the four times of its captions.
+# Readings: the inoculum's radius sqrt(6.25) = 2.5 is a physical length
+# (2.5 / h cells) and is cut beyond 3 r0 as everywhere else; the Set 1 and
+# Set 2 step is 0.02315, the one their captions' times and iteration counts
+# imply (the text rounds it to 0.0231); the sigma0 = 4 sets quote 0.0110.
+# ---------------------------------------------------------------------------
+PAPER_2D = dict(length=680.0, cells=2048, b_max=0.71, r0=2.5, cut=3.0, amp=1.0)
+
+PAPER_SETS = {
+    "set1": dict(sigma0=1.0, n0=0.71, chi=(0.0, 5.0), times=(694.5, 1389.0, 2083.5, 2824.0),
+                 dt=0.02315),
+    "set2": dict(sigma0=1.0, n0=1.07, chi=(0.0, 5.0), times=(115.7, 231.5, 370.4, 509.3),
+                 dt=0.02315),
+    "set3a": dict(sigma0=4.0, n0=0.71, chi=(0.0, 2.5), times=(92.6, 162.0, 231.5, 324.0),
+                  dt=0.0110),
+    "set3b": dict(sigma0=4.0, n0=0.71, chi=(5.0, 7.5), times=(92.6, 162.0, 231.5, 324.0),
+                  dt=0.0110),
+    "set4": dict(sigma0=4.0, n0=1.07, chi=(0.0, 7.5), times=(33.0, 66.0, 88.0, 110.2),
+                 dt=0.0110),
+}
+
+
+def paper_fields(cells, length, n0, b_max=0.71, r0=2.5, cut=3.0):
+    """(b0, n0_field) float32 arrays of shape [cells, cells]: the inoculum of
+    physical radius r0 (r0 / h cells, h = length / cells) about the centre."""
+    h = length / cells
+    b, n, _ = fields(cells, cells, n0, 0.0, 0, b_max=b_max, r0=r0 / h, cut=cut, chunk_rows=cells)
+    return b, n
+
+
+def paper_dt(cells, length, sigma0, n0, dt_paper, amp=1.0, b_max=0.71, D_n=1.0, margin=0.95):
+    """The paper's step where it keeps the explicit bound, else `margin` times
+    the bound; FP32-rounded.
+
+    Bound: h^2 / (4 max(D_n, sigma0 (1 + amp) B^2)) with B = (n0 + b_max) / 2.
+    sigma n b is largest where nutrient has turned into bacteria up to b = n
+    (local kinetics keep b + n <= n0 + b_max, so n b <= B^2), and the noise
+    draws sigma up to sigma0 (1 + amp).  The paper's 0.0110 at sigma0 = 4 and
+    its 0.02315 at (sigma0, n0) = (1, 1.07) exceed this bound; the runs then
+    take the smaller step and keep the captions' physical times."""
+    h = length / cells
+    B = 0.5 * (n0 + b_max)
+    bound = h * h / (4.0 * max(D_n, sigma0 * (1.0 + amp) * B * B))
+    return float(np.float32(min(dt_paper, margin * bound)))
