@@ -379,7 +379,35 @@ def extras(args):
     progress("velocity map: %s" % ex["velocity_map"])
     ex["front1d"] = front1d_speeds()
     progress("1-D fronts: %s" % ex["front1d"])
+    ex["paper_sets_2048"] = paper_sets()
+    progress("paper sets: %s" % ex["paper_sets_2048"])
     return ex
+
+
+def paper_sets():
+    """The paper's 2-D figure sets (Sec. 3) at 2048^2 on L = 680: RK2 with sigma
+    redrawn at every cell and step, each column to its captions' last time;
+    envelope radii, the high/low sensitivity ratio and the shape at that time."""
+    from paper_1301_5058_amd import colony, workload
+    out, cells_steps, gpu_s = {}, 0.0, 0.0
+    for name in workload.PAPER_SETS:
+        res, _ = colony.run_set(name)
+        cols = []
+        for c in res["columns"]:
+            i, r = c["info"], c["snapshots"][-1]
+            cells_steps += i["cells"] ** 2 * i["steps"]
+            gpu_s += i["gpu_s"]
+            cols.append({"chi0": i["chi"], "dt": i["dt"], "steps": i["steps"], "t": round(r["t"], 2),
+                         "r_env": round(r["r_env"], 2), "compactness": round(r["compactness"], 3),
+                         "axis_diag": round(r["axis_diag"], 3),
+                         "arcs_half_r_env": r["rings"][0]["arcs"],
+                         "b_centre_over_peak": round(r["b_centre"] / r["b_peak"], 3),
+                         "tuning": i["tuning"]})
+        out[name] = {"sigma0": res["sigma0"], "n0": res["n0"], "columns": cols,
+                     "r_env_ratio": [round(v, 3) for v in res["r_env_ratio"]]}
+    return {"cells": workload.PAPER_2D["cells"], "length": workload.PAPER_2D["length"],
+            "gpu_s": round(gpu_s, 2), "gcell_steps_s": round(cells_steps / gpu_s * 1e-9, 1),
+            "sets": out}
 
 
 def front1d_speeds():
