@@ -398,6 +398,7 @@ def paper_sets():
             cells_steps += i["cells"] ** 2 * i["steps"]
             gpu_s += i["gpu_s"]
             cols.append({"chi0": i["chi"], "dt": i["dt"], "steps": i["steps"], "t": round(r["t"], 2),
+                         "envelope_speed": None if i["speed"] is None else round(i["speed"], 5),
                          "r_env": round(r["r_env"], 2), "compactness": round(r["compactness"], 3),
                          "axis_diag": round(r["axis_diag"], 3),
                          "arcs_half_r_env": r["rings"][0]["arcs"],

@@ -25,6 +25,9 @@ is copied to the host and described by `morphology`:
   b_centre     b at the centre, b_peak its maximum (a depression at the centre
                shows as b_centre < b_peak)
 
+and each run by its envelope speed: the least-squares slope of r_env(t) over
+the caption times at which the envelope has not reached the wall.
+
 The paper prints pictures, not numbers; what it states (faster envelopes with
 chi0, branches merging into a disk at sigma0 = 4, n0 = 0.71, chi0 = 7.5, disks
 at n0 = 1.07, sigma0 = 4) is read off these quantities.
@@ -95,6 +98,18 @@ def morphology(b, h, b_thr, cx=None, cy=None, rings=RING_FRACTIONS):
     return out
 
 
+def envelope_speed(snapshots, half_side, wall=0.95):
+    """Least-squares slope of r_env against t over the snapshots whose envelope
+    has not reached `wall` of the half side (None with fewer than two)."""
+    pts = [(r["t"], r["r_env"]) for r in snapshots if r["r_env"] < wall * half_side]
+    if len(pts) < 2:
+        return None
+    t = np.array([p[0] for p in pts])
+    r = np.array([p[1] for p in pts])
+    tc = t - t.mean()
+    return float(np.dot(tc, r - r.mean()) / np.dot(tc, tc))
+
+
 def run_case(sigma0, n0, chi, times, dt_paper, cells=2048, length=680.0, seed=1,
              precision="fp32", keep_fields=False, log=None, chunk_cell_steps=5e12):
     """One run of the paper's set-up; returns (records, fields) with one record
@@ -160,6 +175,7 @@ def run_case(sigma0, n0, chi, times, dt_paper, cells=2048, length=680.0, seed=1,
                     gcell_s=cells * cells * done / (gpu_ms * 1e-3) * 1e-9 if gpu_ms > 0 else 0.0)
         for r in recs:
             r.update(chi=chi)
+        info["speed"] = envelope_speed(recs, 0.5 * length)
         return dict(info=info, snapshots=recs), keep
     finally:
         S.close()
@@ -270,9 +286,10 @@ def main(argv=None):
             name, res["chi"][1], res["chi"][0], " ".join("%.2f" % r for r in res["r_env_ratio"])))
         for c in res["columns"]:
             i = c["info"]
-            log("  chi0=%g: dt=%.6g (paper %.6g), %d steps in %.2f s of GPU time, %.1f GCell/s, "
-                "tuning %s" % (i["chi"], i["dt"], i["dt_paper"], i["steps"], i["gpu_s"], i["gcell_s"],
-                               tuple(i["tuning"])))
+            log("  chi0=%g: envelope speed %s, dt=%.6g (paper %.6g), %d steps in %.2f s of GPU "
+                "time, %.1f GCell/s, tuning %s"
+                % (i["chi"], "-" if i["speed"] is None else "%.4f" % i["speed"], i["dt"],
+                   i["dt_paper"], i["steps"], i["gpu_s"], i["gcell_s"], tuple(i["tuning"])))
         if a.png:
             os.makedirs(a.png, exist_ok=True)
             save_png(os.path.join(a.png, "%s.png" % name), fields)

@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 from paper_1301_5058_amd import workload
-from paper_1301_5058_amd.colony import morphology
+from paper_1301_5058_amd.colony import envelope_speed, morphology
 
 
 def _grid(side):
@@ -131,3 +131,13 @@ def test_paper_time_steps():
         assert dt < s["dt"] and dt == pytest.approx(0.95 * bound, rel=1e-6)
         # the library's own check on the initial fields: sigma0 (1 + a) max(n b)
         assert dt <= h * h / (4 * max(1.0, 2 * s["sigma0"] * s["n0"] * 0.71))
+
+
+def test_envelope_speed_is_the_least_squares_slope_before_the_wall():
+    snaps = [dict(t=t, r_env=5.0 + 0.25 * t + e) for t, e in ((10, 0.1), (20, -0.1), (30, 0.0))]
+    # slope 0.25 plus that of the offsets: (-10 * 0.1 + 10 * 0.0) / 200 = -0.005
+    assert envelope_speed(snaps, 100.0) == pytest.approx(0.245, abs=1e-12)
+    # a snapshot at the wall is left out; with one left there is no slope
+    snaps.append(dict(t=400.0, r_env=99.0))
+    assert envelope_speed(snaps, 100.0) == pytest.approx(0.245, abs=1e-12)
+    assert envelope_speed(snaps[:1] + snaps[3:], 100.0) is None
