@@ -643,9 +643,9 @@ int kb_set_fields(kb_batch *b, int32_t k, const float *b0, const float *n0, cons
     const BInst &H = b->hinst[k];
     const hipMemcpyKind kind = mem == KC_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
     const size_t sp = (size_t)I.nx * sizeof(float), dp = (size_t)H.pitch * sizeof(float);
-    KB_HIP(b, hipMemcpy2DAsync(H.b[b->cur], dp, b0, sp, sp, I.ny, kind, b->stream));
-    KB_HIP(b, hipMemcpy2DAsync(H.n[b->cur], dp, n0, sp, sp, I.ny, kind, b->stream));
-    KB_HIP(b, hipMemcpy2DAsync(H.sg, dp, sigma, sp, sp, I.ny, kind, b->stream));
+    KB_HIP(b, kc::copy_rows(H.b[b->cur], dp, b0, sp, sp, I.ny, kind, b->stream));
+    KB_HIP(b, kc::copy_rows(H.n[b->cur], dp, n0, sp, sp, I.ny, kind, b->stream));
+    KB_HIP(b, kc::copy_rows(H.sg, dp, sigma, sp, sp, I.ny, kind, b->stream));
     KB_HIP(b, hipStreamSynchronize(b->stream));
     b->has_fields[k] = 1;
     b->nsamp = 0;
@@ -779,9 +779,9 @@ int kb_get_fields(kb_batch *b, int32_t k, float *bo, float *no, int mem)
     const hipMemcpyKind kind = mem == KC_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
     const size_t dp = (size_t)H.nx * sizeof(float), sp = (size_t)H.pitch * sizeof(float);
     if (bo)
-        KB_HIP(b, hipMemcpy2DAsync(bo, dp, H.b[b->cur], sp, dp, H.ny, kind, b->stream));
+        KB_HIP(b, kc::copy_rows(bo, dp, H.b[b->cur], sp, dp, H.ny, kind, b->stream));
     if (no)
-        KB_HIP(b, hipMemcpy2DAsync(no, dp, H.n[b->cur], sp, dp, H.ny, kind, b->stream));
+        KB_HIP(b, kc::copy_rows(no, dp, H.n[b->cur], sp, dp, H.ny, kind, b->stream));
     KB_HIP(b, hipStreamSynchronize(b->stream));
     return KC_OK;
 }

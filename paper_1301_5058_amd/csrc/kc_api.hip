@@ -210,12 +210,13 @@ template <typename R> int step_impl(kc_ctx *c, int64_t nsteps)
     return KC_OK;
 }
 
+// s null: sigma = 1 everywhere
 template <typename R> int check_host(int nx, int ny, const R *b, const R *n, const R *s, double *mx)
 {
     const size_t cells = (size_t)nx * (size_t)ny;
     double m = 0.0;
     for (size_t i = 0; i < cells; ++i) {
-        const double bv = b[i], nv = n[i], sv = s[i];
+        const double bv = b[i], nv = n[i], sv = s ? s[i] : 1.0;
         if (!(isfinite(bv) && isfinite(nv) && isfinite(sv)) || bv < 0 || nv < 0 || sv < 0)
             return KC_ENONFINITE;
         const double v = sv * nv * bv;
@@ -455,37 +456,19 @@ int kc_set_fields(kc_ctx *c, const void *b0, const void *n0, const void *sigma, 
     if (mem != KC_MEM_HOST && mem != KC_MEM_DEVICE)
         return fail(c, KC_EINVAL, "bad memory kind %d", mem);
     const size_t cells = (size_t)c->nx * c->ny;
-    // with per-step noise the check sees sigma = 1 and the stability bound is
-    // scaled by the largest sigma the noise can draw, sigma0 (1 + amp)
-    std::vector<unsigned char> ones;
-    void *dones = nullptr;
-    if (noise) {
-        ones.resize(cells * c->esz);
-        for (size_t i = 0; i < cells; ++i) {
-            if (c->esz == 4) {
-                const float v = 1.0f;
-                memcpy(&ones[i * 4], &v, 4);
-            } else {
-                const double v = 1.0;
-                memcpy(&ones[i * 8], &v, 8);
-            }
-        }
-        sigma = ones.data();
-        if (mem == KC_MEM_DEVICE) {
-            KC_HIP(c, hipMalloc(&dones, cells * c->esz));
-            const hipError_t e =
-                hipMemcpy(dones, ones.data(), cells * c->esz, hipMemcpyHostToDevice);
-            if (e != hipSuccess) {
-                (void)hipFree(dones);
-                return hipfail(c, e, "noise check staging");
-            }
-            sigma = dones;
-        }
-    }
+    // with per-step noise the check takes sigma = 1 (a null sigma) and the
+    // stability bound is scaled by the largest sigma the noise can draw,
+    // sigma0 (1 + amp)
+    if (noise)
+        sigma = nullptr;
     double mx = 0.0;
     int rc = KC_OK;
     if (mem == KC_MEM_HOST) {
-        rc = kc_check_fields(c->nx, c->ny, c->p.precision, b0, n0, sigma, &mx);
+        rc = c->p.precision == KC_FP32
+                 ? check_host<float>(c->nx, c->ny, (const float *)b0, (const float *)n0,
+                                     (const float *)sigma, &mx)
+                 : check_host<double>(c->nx, c->ny, (const double *)b0, (const double *)n0,
+                                      (const double *)sigma, &mx);
         if (rc != KC_OK)
             rc = fail(c, rc, "input fields rejected: %s", kc_strerror(rc));
     } else {
@@ -516,8 +499,6 @@ int kc_set_fields(kc_ctx *c, const void *b0, const void *n0, const void *sigma, 
                           nbad);
         }
     }
-    if (dones)
-        (void)hipFree(dones);
     if (rc != KC_OK)
         return rc;
     if (noise)
@@ -530,10 +511,10 @@ int kc_set_fields(kc_ctx *c, const void *b0, const void *n0, const void *sigma, 
     const hipMemcpyKind kind = mem == KC_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
     const size_t spitch = (size_t)c->nx * c->esz, dpitch = (size_t)c->pitch * c->esz;
     c->cur = 0;
-    KC_HIP(c, hipMemcpy2DAsync(c->b[0], dpitch, b0, spitch, spitch, c->ny, kind, c->stream));
-    KC_HIP(c, hipMemcpy2DAsync(c->n[0], dpitch, n0, spitch, spitch, c->ny, kind, c->stream));
+    KC_HIP(c, kc::copy_rows(c->b[0], dpitch, b0, spitch, spitch, c->ny, kind, c->stream));
+    KC_HIP(c, kc::copy_rows(c->n[0], dpitch, n0, spitch, spitch, c->ny, kind, c->stream));
     if (!noise)
-        KC_HIP(c, hipMemcpy2DAsync(c->sg, dpitch, sigma, spitch, spitch, c->ny, kind, c->stream));
+        KC_HIP(c, kc::copy_rows(c->sg, dpitch, sigma, spitch, spitch, c->ny, kind, c->stream));
     KC_HIP(c, hipStreamSynchronize(c->stream));
     c->has_fields = true;
     c->steps = c->p.step0;
@@ -606,9 +587,9 @@ int kc_get_fields(kc_ctx *c, void *b, void *n, int mem)
     const hipMemcpyKind kind = mem == KC_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
     const size_t dpitch = (size_t)c->nx * c->esz, spitch = (size_t)c->pitch * c->esz;
     if (b)
-        KC_HIP(c, hipMemcpy2DAsync(b, dpitch, c->b[c->cur], spitch, dpitch, c->ny, kind, c->stream));
+        KC_HIP(c, kc::copy_rows(b, dpitch, c->b[c->cur], spitch, dpitch, c->ny, kind, c->stream));
     if (n)
-        KC_HIP(c, hipMemcpy2DAsync(n, dpitch, c->n[c->cur], spitch, dpitch, c->ny, kind, c->stream));
+        KC_HIP(c, kc::copy_rows(n, dpitch, c->n[c->cur], spitch, dpitch, c->ny, kind, c->stream));
     KC_HIP(c, hipStreamSynchronize(c->stream));
     return KC_OK;
 }

@@ -8,7 +8,8 @@
 // diag_final:   one block folds the partials in a fixed order and writes
 //   {t, h^2 sum b, h^2 sum n, h sqrt(max d^2), h sqrt(count / pi)}.
 // check_partial: input validation of dense device arrays: per block, the
-//   count of NaN / Inf / negative entries and the max of sigma n b.
+//   count of NaN / Inf / negative entries and the max of sigma n b (sigma taken
+//   as 1 when its pointer is null).
 #include "kc_internal.h"
 
 namespace kc {
@@ -135,7 +136,7 @@ __global__ __launch_bounds__(256) void check_partial(const R *b, const R *n, con
     double nbad = 0.0, mx = 0.0, unused = 0.0, unused2 = 0.0;
     const size_t stride = (size_t)gridDim.x * 256;
     for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < cells; i += stride) {
-        const R bv = b[i], nv = n[i], sv = sg[i];
+        const R bv = b[i], nv = n[i], sv = sg ? sg[i] : R(1);
         const bool ok = (bv >= R(0)) && (nv >= R(0)) && (sv >= R(0)) && __builtin_isfinite(bv) &&
                         __builtin_isfinite(nv) && __builtin_isfinite(sv);
         if (!ok)

@@ -14,6 +14,19 @@ namespace kc {
 // pitch is nx rounded up to a multiple of 64 elements, padding kept at 0.
 inline int pitch_for(int nx) { return (nx + 63) / 64 * 64; }
 
+// Copy of `rows` rows of `width` bytes between buffers with row pitches
+// dpitch and spitch, enqueued on s.  When both pitches equal the row width
+// (nx a multiple of 64) it is one linear copy: the same bytes, and 2-D copies
+// to pageable host memory have returned wrong data under rocprofv3 kernel
+// tracing on this ROCm stack while linear ones did not.
+inline hipError_t copy_rows(void *dst, size_t dpitch, const void *src, size_t spitch, size_t width,
+                            size_t rows, hipMemcpyKind kind, hipStream_t s)
+{
+    if (dpitch == width && spitch == width)
+        return hipMemcpyAsync(dst, src, width * rows, kind, s);
+    return hipMemcpy2DAsync(dst, dpitch, src, spitch, width, rows, kind, s);
+}
+
 template <typename R> struct Fields {
     const R *b_in, *n_in, *sg; // current level and agar field sigma
     R *b_out, *n_out;          // next level
@@ -96,7 +109,7 @@ hipError_t launch_diag(const R *b, const R *n, int nx, int ny, int pitch, double
 
 // Input check of dense device arrays: block k writes parts[2k] = number of
 // NaN / Inf / negative entries it saw and parts[2k+1] = its max of sigma n b,
-// for k < check_parts(cells).
+// for k < check_parts(cells); a null sg counts as sigma = 1 everywhere.
 int check_parts(size_t cells);
 template <typename R>
 hipError_t launch_check(const R *b, const R *n, const R *sg, size_t cells, double *parts,
