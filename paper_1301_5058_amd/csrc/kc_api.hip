@@ -132,8 +132,9 @@ template <typename R> Coef<R> make_coef(const kc_ctx *c)
 template <typename R> kc::Noise<R> make_noise(const kc_ctx *c)
 {
     kc::Noise<R> z;
-    z.sigma0 = (R)c->p.sigma0;
-    z.amp = (R)c->p.noise_amp;
+    // sigma / 2 = h0 + h1 (k1 + k2): sigma0 (1 + a ((k1 + k2) 2^-16 - 1)) / 2
+    z.h0 = (R)(0.5 * c->p.sigma0 * (1.0 - c->p.noise_amp));
+    z.h1 = (R)(c->p.sigma0 * c->p.noise_amp * 0x1p-17);
     z.k0 = (uint32_t)(c->p.noise_seed & 0xffffffffu);
     z.k1 = (uint32_t)(c->p.noise_seed >> 32);
     z.s_lo = (uint32_t)((uint64_t)c->steps & 0xffffffffu);

@@ -100,11 +100,13 @@ template <typename R> __device__ __forceinline__ R rk2_average(R u, R e2)
 // numbers: as easy as 1, 2, 3", SC 2011).  Counter (x / 4, y, step low word,
 // step high word), key (seed low word, seed high word); cell x takes output
 // word x mod 4, and its two 16-bit halves k1, k2 give Delta = (k1 + k2) 2^-16
-// - 1, exact in either precision.
+// - 1.  sigma / 2 is affine in k = k1 + k2 (an integer below 2^17, exact in
+// either precision): sigma / 2 = h0 + h1 k with h0 = sigma0 (1 - a) / 2 and
+// h1 = sigma0 a 2^-17, one FMA per cell.
 // ---------------------------------------------------------------------------
 template <typename R> struct Noise {
-    R sigma0, amp;
-    uint32_t k0, k1;    // seed words
+    R h0, h1;            // sigma / 2 = h0 + h1 (k1 + k2)
+    uint32_t k0, k1;     // seed words
     uint32_t s_lo, s_hi; // time step of the launch's first step
 };
 
@@ -134,11 +136,10 @@ __device__ __forceinline__ void noise_step(const Noise<R> &z, int ds, uint32_t &
     hi = z.s_hi + (lo < z.s_lo ? 1u : 0u);
 }
 
-// sigma of one generator word.
-template <typename R> __device__ __forceinline__ R noise_sigma(const Noise<R> &z, uint32_t w)
+// sigma / 2 of one generator word.
+template <typename R> __device__ __forceinline__ R noise_half(const Noise<R> &z, uint32_t w)
 {
-    const R delta = (R)((w & 0xffffu) + (w >> 16)) * R(1.0 / 65536.0) - R(1);
-    return z.sigma0 * (R(1) + z.amp * delta);
+    return fmaR(z.h1, (R)((w & 0xffffu) + (w >> 16)), z.h0);
 }
 
 // sigma / 2 of cells x4 .. x4 + VEC - 1 of row y at step ds (x4 a multiple of VEC;
@@ -151,14 +152,14 @@ __device__ __forceinline__ void noise_half_sigma(const Noise<R> &z, int ds, int 
     uint32_t c0 = (uint32_t)x4 >> 2, c1 = (uint32_t)y, c2 = lo, c3 = hi;
     philox4x32_10(c0, c1, c2, c3, z.k0, z.k1);
     if (VEC == 4) { // x4 is a multiple of 4: the whole call
-        out[0] = R(0.5) * noise_sigma<R>(z, c0);
-        out[1] = R(0.5) * noise_sigma<R>(z, c1);
-        out[2 % VEC] = R(0.5) * noise_sigma<R>(z, c2);
-        out[3 % VEC] = R(0.5) * noise_sigma<R>(z, c3);
+        out[0] = noise_half<R>(z, c0);
+        out[1] = noise_half<R>(z, c1);
+        out[2 % VEC] = noise_half<R>(z, c2);
+        out[3 % VEC] = noise_half<R>(z, c3);
     } else { // VEC = 2: words 0, 1 or 2, 3
         const bool upper = (x4 & 2) != 0;
-        out[0] = R(0.5) * noise_sigma<R>(z, upper ? c2 : c0);
-        out[1 % VEC] = R(0.5) * noise_sigma<R>(z, upper ? c3 : c1);
+        out[0] = noise_half<R>(z, upper ? c2 : c0);
+        out[1 % VEC] = noise_half<R>(z, upper ? c3 : c1);
     }
 }
 
@@ -172,7 +173,7 @@ __device__ __forceinline__ R noise_half_sigma1(const Noise<R> &z, int ds, int x,
     philox4x32_10(c0, c1, c2, c3, z.k0, z.k1);
     const int q = x & 3;
     const uint32_t w = q == 0 ? c0 : q == 1 ? c1 : q == 2 ? c2 : c3;
-    return R(0.5) * noise_sigma<R>(z, w);
+    return noise_half<R>(z, w);
 }
 
 // ---------------------------------------------------------------------------
