@@ -42,6 +42,12 @@ OPS_PER_CELL_UPDATE = 33
 # of b and n
 OPS_PER_RK2_UPDATE = 2 * OPS_PER_CELL_UPDATE + 4
 BYTES_PER_CELL_LAUNCH = {"fp32": 20, "fp64": 40}  # read b, n, sigma; write b', n'
+# per-step agar noise: sigma is drawn in the kernel, not read (read b, n; write b', n'),
+# and each cell-update draws it: Philox4x32-10 is 10 rounds of two 32 x 32 -> 64
+# multiplies and two three-way XORs per call of four cells (10 per cell), then the
+# sum of the word's halves, its conversion and one FMA
+BYTES_PER_CELL_LAUNCH_NOISE = {"fp32": 16, "fp64": 32}
+OPS_PER_NOISE_DRAW = 13
 # per-step agar noise of the 4096^2 workload: sigma = 1 + 0.5 Delta, redrawn every step
 NOISE_4096 = {"sigma0": 1.0, "amp": 0.5, "seed": 2013}
 SAMPLE_EVERY = 100
@@ -125,10 +131,13 @@ def launch_probe(S, stream, launches=60):
     return e0.elapsed_time(e1) / launches
 
 
-def roofline(precision, cells, tsteps, launch_ms, ops_per_update=OPS_PER_CELL_UPDATE):
+def roofline(precision, cells, tsteps, launch_ms, ops_per_update=OPS_PER_CELL_UPDATE,
+             bytes_per_cell=None):
     """Roofline of the fused step kernel: the bound (HBM or VALU) with the
     larger fraction of its peak is reported as the kernel's bound."""
-    bytes_per = BYTES_PER_CELL_LAUNCH[precision] * cells
+    if bytes_per_cell is None:
+        bytes_per_cell = BYTES_PER_CELL_LAUNCH[precision]
+    bytes_per = bytes_per_cell * cells
     gbs = bytes_per / (launch_ms / 1e3) / 1e9
     tops = ops_per_update * cells * tsteps / (launch_ms / 1e3) / 1e12
     hbm = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -270,13 +279,18 @@ def single_variant(nx, n0, a, chi, precision, steps, tune_effort=0, integrator="
     ms = timed_run(S, stream, steps)
     lm = launch_probe(S, stream, 20)
     ops = OPS_PER_RK2_UPDATE if integrator == "rk2" else OPS_PER_CELL_UPDATE
-    rl, _ = roofline(precision, nx * nx, T, lm, ops)
+    nbytes = None
+    if noise is not None:
+        ops += OPS_PER_NOISE_DRAW
+        nbytes = BYTES_PER_CELL_LAUNCH_NOISE[precision]
+    rl, other = roofline(precision, nx * nx, T, lm, ops, nbytes)
     S.close()
     return {"gcell_s": round(nx * nx * steps / (ms / 1e3) / 1e9, 2), "steps": steps,
             "integrator": integrator, "noise": noise is not None, "tsteps": T, "rows": rows,
             "prefetch": pf,
             "launch_us": round(lm * 1e3, 2), "roofline_bound": rl["bound"],
-            "roofline_frac": rl["frac"]}
+            "roofline_frac": rl["frac"], "other_bound": other["bound"],
+            "other_frac": other["frac"]}
 
 
 def hires(steps):

@@ -110,6 +110,15 @@ template <typename R> struct Noise {
     uint32_t s_lo, s_hi; // time step of the launch's first step
 };
 
+// a ^ b ^ k in one v_bitop3_b32 (truth table 0x96 = 0xF0 ^ 0xCC ^ 0xAA); k is
+// wave-uniform (a key word).  The compiler emits two XORs for this chain.
+__device__ __forceinline__ uint32_t xor3_uniform(uint32_t a, uint32_t b, uint32_t k)
+{
+    uint32_t r;
+    asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x96" : "=v"(r) : "v"(a), "v"(b), "s"(k));
+    return r;
+}
+
 __device__ __forceinline__ void philox4x32_10(uint32_t &c0, uint32_t &c1, uint32_t &c2,
                                               uint32_t &c3, uint32_t k0, uint32_t k1)
 {
@@ -117,8 +126,8 @@ __device__ __forceinline__ void philox4x32_10(uint32_t &c0, uint32_t &c1, uint32
     for (int r = 0; r < 10; ++r) {
         const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
         const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
-        const uint32_t x0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
-        const uint32_t x2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        const uint32_t x0 = xor3_uniform((uint32_t)(p1 >> 32), c1, k0);
+        const uint32_t x2 = xor3_uniform((uint32_t)(p0 >> 32), c3, k1);
         c1 = (uint32_t)p1;
         c3 = (uint32_t)p0;
         c0 = x0;
