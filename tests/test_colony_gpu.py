@@ -105,3 +105,26 @@ def test_colony_runner_records():
         out[chi] = snaps[-1]["r_env"]
     print("r_env at t=20: chi0=0 %.2f, chi0=7.5 %.2f" % (out[0.0], out[7.5]))
     assert out[7.5] > out[0.0]
+
+
+def test_grid_study_runs_each_mesh_at_its_own_bound():
+    """The grid-size study (Sec. 3.2) on two meshes of one square: each mesh
+    takes the step of its own explicit bound, reaches the same caption times,
+    and the colony's physical size agrees between the meshes."""
+    L = 512 * H
+    res, fields = colony.grid_study("set4", 0.0, [256, 512], length=L, keep_fields=True)
+    assert res["cells"] == [256, 512] and len(fields) == 2
+    a, b = (c["info"] for c in res["columns"])
+    assert a["h"] == pytest.approx(2 * b["h"]) and a["dt"] > b["dt"]
+    s = workload.PAPER_SETS["set4"]
+    for c in res["columns"]:
+        i = c["info"]
+        assert i["dt"] == workload.paper_dt(i["cells"], L, s["sigma0"], s["n0"], s["dt"])
+        assert [r["t_caption"] for r in c["snapshots"]] == list(s["times"])
+        for r in c["snapshots"]:
+            assert abs(r["t"] - r["t_caption"]) <= i["dt"]
+    # first caption time, before either colony reaches the wall: radii within 25 %
+    ra, rb = (c["snapshots"][0]["r_env"] for c in res["columns"])
+    print("set4 chi0=0 r_env at t=33: 256^2 %.2f, 512^2 %.2f" % (ra, rb))
+    assert 0 < ra < 0.95 * L / 2 and 0 < rb < 0.95 * L / 2
+    assert abs(ra - rb) <= 0.25 * rb
