@@ -68,11 +68,22 @@ def _create(nx=16, ny=16, h=1.0, dt=0.1, **kw):
                                 dict(dt=0.0), dict(dt=-1.0), dict(dt=math.inf),
                                 dict(D_n=-1.0), dict(theta=-0.1), dict(kappa=math.nan),
                                 dict(chi=-2.0), dict(chi_law=7), dict(precision=3),
-                                dict(nx=1 << 21), dict(step0=-1), dict(b_thr=math.nan)])
+                                dict(nx=1 << 21), dict(step0=-1), dict(b_thr=math.nan),
+                                dict(integrator=2), dict(noise=2),
+                                dict(noise=1, noise_amp=1.0 + 1e-12), dict(noise=1, noise_amp=-0.1),
+                                dict(noise=1, noise_amp=math.nan), dict(noise=1, sigma0=0.0),
+                                dict(noise=1, sigma0=math.inf)])
 def test_create_rejects_bad_arguments(kw):
     rc, ctx = _create(**kw)
     assert rc == N.KC_EINVAL
     assert not ctx.value
+
+
+def test_create_accepts_the_papers_full_noise_amplitude():
+    # sigma = sigma0 (1 + Delta) (Sec. 3): amplitude 1 passes the argument checks
+    # (without a GPU the call then fails with KC_EHIP, with one it succeeds)
+    rc, _ = _create(noise=1, noise_amp=1.0, sigma0=4.0, integrator=1)
+    assert rc != N.KC_EINVAL
 
 
 def test_create_rejects_null_outputs():
