@@ -157,9 +157,10 @@ def timed_run(S, stream, steps, series=None):
     left, i = steps, 0
     while left > 0:
         k = min(SAMPLE_EVERY, left)
-        S.step(k)
         if series is not None:
-            S.diagnostics_device(series[i])
+            S.step_sample(k, series[i])  # diagnostics fused into the last launch
+        else:
+            S.step(k)
         left -= k
         i += 1
     e1.record(stream)

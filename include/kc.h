@@ -120,7 +120,8 @@ int kc_create(const kc_grid *g, double h, double dt, const kc_params *p, void *h
  * the largest sigma the noise can draw, sigma0 (1 + noise_amp). */
 int kc_set_fields(kc_ctx *ctx, const void *b0, const void *n0, const void *sigma, int mem);
 
-/* Advance nsteps >= 0 forward-Euler steps (enqueued, asynchronous). */
+/* Advance nsteps >= 0 time steps of the context's integrator (enqueued,
+ * asynchronous). */
 int kc_step(kc_ctx *ctx, int64_t nsteps);
 
 /* Diagnostics of the current level, synchronous:
@@ -134,6 +135,19 @@ int kc_diagnostics(kc_ctx *ctx, double *mass, double *nutrient, double *envelope
  * reaches it; area_radius = h sqrt(N / pi), N the number of cells with
  * b >= b_thr (the radius of a disc of the colony's area). */
 int kc_diagnostics_device(kc_ctx *ctx, double *dev_out5);
+
+/* kc_step(ctx, nsteps) followed by kc_diagnostics_device(ctx, dev_out5), with
+ * the diagnostics fused into the last step launch: every wavefront strip folds
+ * the cells it stores into double partials and one small pass folds those in a
+ * fixed order, so no separate read of the fields is made (mass and nutrient
+ * are the integrals whose sum the model conserves without growth, Sec. 4.1,
+ * eq. mass-conser).  nsteps >= 1 (KC_EINVAL otherwise;
+ * dev_out5 non-NULL).  Time and radii equal kc_diagnostics_device's; mass and
+ * nutrient are the same sums in another order (equal to about 1e-15
+ * relative).  Enqueued, asynchronous.  The first call for a strip count above
+ * those seen before allocates a partials buffer of 32 bytes per strip.  With
+ * the reference kernel selected it runs kc_step and kc_diagnostics_device. */
+int kc_step_sample(kc_ctx *ctx, int64_t nsteps, double *dev_out5);
 
 /* Copy the current level out (synchronous).  Either pointer may be NULL. */
 int kc_get_fields(kc_ctx *ctx, void *b, void *n, int mem);

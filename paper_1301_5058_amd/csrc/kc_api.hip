@@ -37,6 +37,8 @@ struct kc_ctx {
     bool ref = false;
     double *dparts = nullptr; // diagnostics partials, then out5 (5 doubles)
     double *dout5 = nullptr;
+    double *sparts = nullptr; // per-strip partials of a fused sampled step
+    size_t sparts_cap = 0;    // in strips
     double *hout = nullptr; // pinned host staging (input check partials, out5)
     std::string err;
 };
@@ -156,7 +158,10 @@ template <typename R> Fields<R> make_fields(const kc_ctx *c)
     return f;
 }
 
-template <typename R> int step_impl(kc_ctx *c, int64_t nsteps)
+// nsteps steps; with dev_out5 non-null (fused kernel only) the last launch also
+// folds the level it stores into per-strip partials and a final pass writes the
+// diagnostics of that level to dev_out5.
+template <typename R> int step_impl(kc_ctx *c, int64_t nsteps, double *dev_out5 = nullptr)
 {
     const Coef<R> k = make_coef<R>(c);
     const int integ = c->p.integrator;
@@ -199,8 +204,32 @@ template <typename R> int step_impl(kc_ctx *c, int64_t nsteps)
             kc::Tuning t = c->tune;
             const int64_t want = nsteps < t.tsteps ? nsteps : t.tsteps;
             t.tsteps = kc::stream_depth_at_most((int)want, integ);
-            e = kc::launch_stream<R>(f, k, c->p.chi_law, integ, t, c->stream, zp);
+            kc::DiagReq d{nullptr, c->p.b_thr, c->p.cx, c->p.cy};
+            int nstrips = 0;
+            if (dev_out5 && t.tsteps == nsteps) {
+                // the last launch: strip partials of the level it stores
+                nstrips = kc::stream_geom(c->p.precision, kc::stream_levels(integ, t.tsteps),
+                                          c->nx, c->ny, t.rows)
+                              .nstrips;
+                if ((size_t)nstrips > c->sparts_cap) {
+                    if (c->sparts) {
+                        KC_HIP(c, hipStreamSynchronize(c->stream));
+                        KC_HIP(c, hipFree(c->sparts));
+                        c->sparts = nullptr;
+                        c->sparts_cap = 0;
+                    }
+                    KC_HIP(c, hipMalloc((void **)&c->sparts, (size_t)nstrips * 4 * sizeof(double)));
+                    c->sparts_cap = (size_t)nstrips;
+                }
+                d.parts = c->sparts;
+            }
+            e = kc::launch_stream<R>(f, k, c->p.chi_law, integ, t, c->stream, zp,
+                                     d.parts ? &d : nullptr);
             adv = t.tsteps;
+            if (e == hipSuccess && d.parts) {
+                const double tt = (double)(c->steps + adv) * c->dt;
+                e = kc::launch_diag_fold(d.parts, nstrips, c->h, tt, dev_out5, c->stream);
+            }
         }
         if (e != hipSuccess)
             return hipfail(c, e, "step kernel launch");
@@ -436,7 +465,7 @@ void kc_destroy(kc_ctx *c)
         return;
     if (c->stream || c->b[0])
         (void)hipStreamSynchronize(c->stream);
-    for (void *q : {c->b[0], c->n[0], c->b[1], c->n[1], c->sg, c->b1, c->n1})
+    for (void *q : {c->b[0], c->n[0], c->b[1], c->n[1], c->sg, c->b1, c->n1, (void *)c->sparts})
         if (q)
             (void)hipFree(q);
     if (c->dparts)
@@ -532,6 +561,24 @@ int kc_step(kc_ctx *c, int64_t nsteps)
     if (!c->has_fields)
         return fail(c, KC_ESTATE, "kc_step before kc_set_fields");
     return c->p.precision == KC_FP32 ? step_impl<float>(c, nsteps) : step_impl<double>(c, nsteps);
+}
+
+int kc_step_sample(kc_ctx *c, int64_t nsteps, double *dev_out5)
+{
+    if (!c || !dev_out5)
+        return KC_EINVAL;
+    c->err.clear();
+    if (nsteps < 1)
+        return fail(c, KC_EINVAL, "kc_step_sample needs at least one step");
+    if (!c->has_fields)
+        return fail(c, KC_ESTATE, "kc_step_sample before kc_set_fields");
+    if (c->ref) {
+        // the reference kernel has no fused diagnostics: step, then the separate pass
+        const int rc = kc_step(c, nsteps);
+        return rc != KC_OK ? rc : kc_diagnostics_device(c, dev_out5);
+    }
+    return c->p.precision == KC_FP32 ? step_impl<float>(c, nsteps, dev_out5)
+                                     : step_impl<double>(c, nsteps, dev_out5);
 }
 
 int kc_diagnostics_device(kc_ctx *c, double *dev_out5)

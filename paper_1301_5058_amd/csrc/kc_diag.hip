@@ -6,7 +6,8 @@
 //   shuffles) then a fixed LDS tree, so the result is the same bits on every
 //   run for a given grid.
 // diag_final:   one block folds the partials in a fixed order and writes
-//   {t, h^2 sum b, h^2 sum n, h sqrt(max d^2), h sqrt(count / pi)}.
+//   {t, h^2 sum b, h^2 sum n, h sqrt(max d^2), h sqrt(count / pi)}; it also
+//   folds the per-strip partials that a fused step launch writes.
 // check_partial: input validation of dense device arrays: per block, the
 //   count of NaN / Inf / negative entries and the max of sigma n b (sigma taken
 //   as 1 when its pointer is null).
@@ -108,6 +109,13 @@ __global__ __launch_bounds__(256) void diag_final(const double *parts, int npart
 }
 
 int diag_parts(int ny) { return ny < kDiagBlocks ? ny : kDiagBlocks; }
+
+hipError_t launch_diag_fold(const double *parts, int nparts, double h, double t, double *out5,
+                            hipStream_t s)
+{
+    hipLaunchKernelGGL(diag_final, dim3(1), dim3(256), 0, s, parts, nparts, h, t, out5);
+    return hipGetLastError();
+}
 
 template <typename R>
 hipError_t launch_diag(const R *b, const R *n, int nx, int ny, int pitch, double h, double t,

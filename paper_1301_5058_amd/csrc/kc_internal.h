@@ -53,12 +53,23 @@ struct StreamGeom {
 };
 StreamGeom stream_geom(int precision, int levels, int nx, int ny, int rows);
 
+// Diagnostics fused into a fused-kernel launch: strip k folds the cells it
+// stores into parts[4k .. 4k + 3] = {sum b, sum n, max squared distance from
+// (cx, cy) of a cell with b >= b_thr (-1: none), count of such cells}.
+struct DiagReq {
+    double *parts;
+    double b_thr, cx, cy;
+};
+
 // One launch advancing t.tsteps steps of `integrator` with the fused kernel;
 // with z non-null the agar field is redrawn at every step (z's step words are
-// the launch's first step) and f.sg is not read.
+// the launch's first step) and f.sg is not read; with d non-null the launch
+// also writes the diagnostics partials of the level it stores (4 doubles per
+// strip, stream_geom(...).nstrips strips).
 template <typename R>
 hipError_t launch_stream(const Fields<R> &f, const Coef<R> &c, int chi_law, int integrator,
-                         const Tuning &t, hipStream_t s, const Noise<R> *z = nullptr);
+                         const Tuning &t, hipStream_t s, const Noise<R> *z = nullptr,
+                         const DiagReq *d = nullptr);
 // One forward-Euler step with the global-memory reference kernel; with b_avg
 // non-null the result is averaged with (b_avg, n_avg) (Runge-Kutta stage 2);
 // with z non-null sigma is drawn for z's step.
@@ -106,6 +117,10 @@ template <typename R>
 hipError_t launch_diag(const R *b, const R *n, int nx, int ny, int pitch, double h, double t,
                        double b_thr, double cx, double cy, double *parts, double *out5,
                        hipStream_t s);
+// The fixed-order final pass alone, over `nparts` partials of 4 doubles (those
+// of launch_diag or of a launch_stream with diagnostics).
+hipError_t launch_diag_fold(const double *parts, int nparts, double h, double t, double *out5,
+                            hipStream_t s);
 
 // Input check of dense device arrays: block k writes parts[2k] = number of
 // NaN / Inf / negative entries it saw and parts[2k+1] = its max of sigma n b,

@@ -116,6 +116,8 @@ static StepArgs<R> make_args(const Fields<R> &f, const Coef<R> &c)
     a.rows = 1;
     a.nsx = a.nstrips = a.nblocks_padded = 0;
     a.c = c;
+    a.parts = nullptr;
+    a.b_thr = a.cx = a.cy = 0.0;
     return a;
 }
 
@@ -134,7 +136,7 @@ static const void *stream_kernel(int chi_law, int integrator, bool noise, int le
 
 template <typename R>
 hipError_t launch_stream(const Fields<R> &f, const Coef<R> &c, int chi_law, int integrator,
-                         const Tuning &t, hipStream_t s, const Noise<R> *z)
+                         const Tuning &t, hipStream_t s, const Noise<R> *z, const DiagReq *d)
 {
     const int levels = stream_levels(integrator, t.tsteps);
     const void *fn = stream_kernel<R>(chi_law, integrator, z != nullptr, levels, t.prefetch);
@@ -148,6 +150,12 @@ hipError_t launch_stream(const Fields<R> &f, const Coef<R> &c, int chi_law, int 
     a.nsx = g.nsx;
     a.nstrips = g.nstrips;
     a.nblocks_padded = g.nblocks_padded;
+    if (d) {
+        a.parts = d->parts;
+        a.b_thr = d->b_thr;
+        a.cx = d->cx;
+        a.cy = d->cy;
+    }
     void *args[] = {&a};
     return hipLaunchKernel(fn, dim3(g.nblocks_padded), dim3(256), args, 0, s);
 }
@@ -298,9 +306,11 @@ template hipError_t time_stream<double>(const Fields<double> &, const Coef<doubl
                                         const Tuning &, hipStream_t, int, double *,
                                         const Noise<double> *);
 template hipError_t launch_stream<float>(const Fields<float> &, const Coef<float> &, int, int,
-                                         const Tuning &, hipStream_t, const Noise<float> *);
+                                         const Tuning &, hipStream_t, const Noise<float> *,
+                                         const DiagReq *);
 template hipError_t launch_stream<double>(const Fields<double> &, const Coef<double> &, int, int,
-                                          const Tuning &, hipStream_t, const Noise<double> *);
+                                          const Tuning &, hipStream_t, const Noise<double> *,
+                                          const DiagReq *);
 template hipError_t launch_ref<float>(const Fields<float> &, const Coef<float> &, int, hipStream_t,
                                       const float *, const float *, const Noise<float> *);
 template hipError_t launch_ref<double>(const Fields<double> &, const Coef<double> &, int,

@@ -18,6 +18,10 @@ template <typename R> struct StepArgs {
     int nsx, nstrips;   // strips along x, total strips
     int nblocks_padded; // grid size (multiple of 8)
     Coef<R> c;
+    // diagnostics of the stored level, or null: strip k writes {sum b, sum n,
+    // max d^2 (-1: none), count of b >= b_thr} to parts[4k .. 4k + 3]
+    double *parts;
+    double b_thr, cx, cy;
 };
 
 // ---------------------------------------------------------------------------
@@ -44,12 +48,29 @@ __global__ __launch_bounds__(256) void step_stream(StepArgs<R> a)
     sa.rows = a.rows;
     sa.c = a.c;
     sa.z = a.z;
-    sa.b_thr = sa.cx = sa.cy = 0.0;
+    sa.b_thr = a.b_thr;
+    sa.cx = a.cx;
+    sa.cy = a.cy;
     const int sx = strip % a.nsx, sy = strip / a.nsx;
     if (strip_interior<R, T>(sa, sx, sy))
         stream_strip<R, T, LAW, PF, false, RK, NOISE>(sa, sx, sy);
     else
         stream_strip<R, T, LAW, PF, true, RK, NOISE>(sa, sx, sy);
+    if (a.parts) {
+        // fold the cells this strip stored into its partials (no separate pass
+        // over the fields; a wave-uniform test on a kernel argument)
+        DiagAcc acc{0.0, 0.0, -1.0, 0.0};
+        strip_diag<R, T>(sa, sx, sy, acc);
+        const double sb = wave_sum64(acc.sb), sn = wave_sum64(acc.sn);
+        const double m2 = wave_max64(acc.m2), ct = wave_sum64(acc.cnt);
+        if ((threadIdx.x & 63) == 0) {
+            double *q = a.parts + 4 * (size_t)strip;
+            q[0] = sb;
+            q[1] = sn;
+            q[2] = m2;
+            q[3] = ct;
+        }
+    }
 }
 
 // The compiled fused kernel of precision R, integrator RK and noise mode NOISE

@@ -98,6 +98,16 @@ class Solver:
     def step(self, nsteps):
         N.check(N.lib().kc_step(self.ctx, int(nsteps)), self.ctx)
 
+    def step_sample(self, nsteps, out5):
+        """nsteps steps, then {t, mass, nutrient, envelope radius, area radius}
+        of the new level into out5 (a contiguous float64 CUDA tensor of >= 5
+        elements), fused into the last step launch; enqueued."""
+        if out5.dtype != torch.float64 or not out5.is_cuda or out5.numel() < 5 or \
+                not out5.is_contiguous():
+            raise ValueError("out5 must be a contiguous float64 CUDA tensor with >= 5 elements")
+        N.check(N.lib().kc_step_sample(self.ctx, int(nsteps), ctypes.c_void_p(out5.data_ptr())),
+                self.ctx)
+
     def diagnostics(self):
         m, nu, r = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
         N.check(N.lib().kc_diagnostics(self.ctx, ctypes.byref(m), ctypes.byref(nu),
