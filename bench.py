@@ -452,7 +452,7 @@ def main():
     ap.add_argument("--copy-ref-mib", type=int, default=0)
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only; --gpus %d is not supported "
+        print("bench.py: the solver runs on one GPU; --gpus %d is not supported "
               "(the multi-GPU domain decomposition is a design, not code)" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
