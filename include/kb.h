@@ -29,7 +29,12 @@
  * launch and kb_run reports KC_EHIP.  On gfx950 a device-scope release or
  * acquire writes back or invalidates the issuing XCD's L2, once per item, so
  * the persistent mode is slower than per-block launches at every batch size
- * measured; the autotuner always selects per-block launches.
+ * measured; the autotuner always selects per-block launches.  A batch whose
+ * instances are all single rows (ny = 1) of at most 512 cells, such as the
+ * 1-D front experiment of Sec. 4.2, runs each kb_run in one launch outside
+ * the persistent mode: one wavefront per instance keeps its row in registers
+ * for every step and writes the samples; fields and radii are the same as
+ * the per-block launches', mass and nutrient the same sums in another order.
  */
 #ifndef KB_H
 #define KB_H

@@ -21,6 +21,7 @@
 #include <stdarg.h>
 #include <stdio.h>
 
+#include <algorithm>
 #include <new>
 #include <string>
 #include <vector>
@@ -285,6 +286,108 @@ __global__ __launch_bounds__(64) void kb_fit(const double *series, int cap, int 
     }
 }
 
+// ---------------------------------------------------------------------------
+// Single-row batches (every instance 1 x nx, nx <= 64 K, e.g. the 1-D front
+// experiment): one wavefront per instance holds the whole row in registers,
+// K cells per lane, and runs every step and sample of kb_run in one launch.
+// The per-block path would need one launch per time block for a few strips.
+// The cell arithmetic is stream_strip's, with the same face, flux and update
+// calls on the same operands (the vertical faces of a one-row grid carry +0),
+// so the fields are the same bits; samples go to the series like
+// batch_kernel's, the radii identical, the sums in another order.
+// ---------------------------------------------------------------------------
+struct Row1Args {
+    const BInst *inst;
+    double *series;
+    int cap, sample_base, parity0;
+    int sample_every, nsamples;
+    long long step_base;
+};
+
+template <int K, int LAW>
+__global__ __launch_bounds__(64) void batch_row_kernel(Row1Args a)
+{
+    const BInst &I = a.inst[blockIdx.x];
+    const int lane = threadIdx.x;
+    const int x0 = lane * K;
+    const float *bi = I.b[a.parity0], *ni = I.n[a.parity0];
+    float b[K], n[K], sh[K];
+    bool ve[K]; // east face of the cell is interior
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int x = x0 + k;
+        const bool in = x < I.nx;
+        b[k] = in ? bi[x] : 0.f;
+        n[k] = in ? ni[x] : 0.f;
+        sh[k] = in ? 0.5f * I.sg[x] : 0.f;
+        ve[k] = x + 1 < I.nx;
+    }
+    for (int s = 0; s < a.nsamples; ++s) {
+        for (int i = 0; i < a.sample_every; ++i) {
+            float D[K], X[K], gb[K], gn[K];
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+                coef<float, LAW>(sh[k], n[k], b[k], I.c.chi2, D[k], X[k]);
+#pragma unroll
+            for (int k = 0; k + 1 < K; ++k)
+                face<float>(b[k], n[k], D[k], X[k], b[k + 1], n[k + 1], D[k + 1], X[k + 1], ve[k],
+                            gb[k], gn[k]);
+            {
+                const float eb = from_next(b[0]), en = from_next(n[0]);
+                const float eD = from_next(D[0]), eX = from_next(X[0]);
+                face<float>(b[K - 1], n[K - 1], D[K - 1], X[K - 1], eb, en, eD, eX, ve[K - 1],
+                            gb[K - 1], gn[K - 1]);
+            }
+            // the west face of lane 0's first cell is the wall: from_prev gives 0
+            const float wb = from_prev(gb[K - 1]), wn = from_prev(gn[K - 1]);
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const float Fb = net<float>(gb[k], k ? gb[k - 1] : wb, 0.f, 0.f);
+                const float Fn = net<float>(gn[k], k ? gn[k - 1] : wn, 0.f, 0.f);
+                float bo, no;
+                update<float>(b[k], n[k], Fb, Fn, I.c, bo, no);
+                b[k] = bo;
+                n[k] = no;
+            }
+        }
+        // sample: {t, h^2 sum b, h^2 sum n, h sqrt(max d^2), h sqrt(count / pi)}
+        double sb = 0.0, sn = 0.0, m2 = -1.0, ct = 0.0;
+        const double dy = 0.0 - I.cy;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            if (x0 + k < I.nx) {
+                const double bv = (double)b[k];
+                sb += bv;
+                sn += (double)n[k];
+                if (bv >= I.b_thr) {
+                    const double dx = (double)(x0 + k) - I.cx;
+                    m2 = fmax(m2, dx * dx + dy * dy);
+                    ct += 1.0;
+                }
+            }
+        }
+        sb = wave_sum64(sb);
+        sn = wave_sum64(sn);
+        m2 = wave_max64(m2);
+        ct = wave_sum64(ct);
+        if (lane == 0) {
+            double *o = a.series + ((size_t)blockIdx.x * a.cap + a.sample_base + s) * 5;
+            o[0] = (double)(a.step_base + (long long)(s + 1) * a.sample_every) * I.dt;
+            o[1] = I.h * I.h * sb;
+            o[2] = I.h * I.h * sn;
+            o[3] = m2 < 0.0 ? 0.0 : I.h * sqrt(m2);
+            o[4] = I.h * sqrt(ct / 3.14159265358979323846);
+        }
+    }
+    float *bo = I.b[a.parity0 ^ 1], *no = I.n[a.parity0 ^ 1];
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+        if (x0 + k < I.nx) {
+            bo[x0 + k] = b[k];
+            no[x0 + k] = n[k];
+        }
+}
+
 } // namespace kc
 
 using kc::BInst;
@@ -313,6 +416,7 @@ struct kb_batch {
     long long spin_limit = 1ll << 23;
     int S = 0, geom_T = -1;
     bool geom_dirty = true;
+    int row_cells = 0; // > 0: every instance is one row of at most this many (<= 512) cells
     std::string err;
 };
 
@@ -524,6 +628,14 @@ int kb_create(int32_t count, const kb_instance *inst, int32_t chi_law, int32_t m
     b->hinst.resize(count);
     b->rows.resize(count);
     b->has_fields.assign(count, 0);
+    // single-row batches of short rows run in one launch (batch_row_kernel)
+    for (int k = 0; k < count; ++k) {
+        if (inst[k].ny != 1 || inst[k].nx > 512) {
+            b->row_cells = 0;
+            break;
+        }
+        b->row_cells = std::max(b->row_cells, (int)inst[k].nx);
+    }
 
     // arena: 5 padded fields per instance, each 256-byte aligned
     size_t total = 0;
@@ -673,6 +785,36 @@ int kb_run(kb_batch *b, int64_t nsteps, int32_t sample_every)
                      (long long)ns, b->cap - b->nsamp);
     if (nsteps == 0)
         return KC_OK;
+    if (!b->persistent && b->row_cells > 0) {
+        // every instance a single row: the whole run in one launch
+        kc::Row1Args r;
+        r.inst = b->dinst;
+        r.series = b->dseries;
+        r.cap = b->cap;
+        r.sample_base = b->nsamp;
+        r.parity0 = b->cur;
+        r.sample_every = sample_every;
+        r.nsamples = (int)ns;
+        r.step_base = b->steps;
+        const dim3 grid((unsigned)b->count), block(64);
+        const int K = b->row_cells <= 256 ? 4 : 8;
+        if (b->law == 0) {
+            if (K == 4)
+                hipLaunchKernelGGL((kc::batch_row_kernel<4, 0>), grid, block, 0, b->stream, r);
+            else
+                hipLaunchKernelGGL((kc::batch_row_kernel<8, 0>), grid, block, 0, b->stream, r);
+        } else {
+            if (K == 4)
+                hipLaunchKernelGGL((kc::batch_row_kernel<4, 1>), grid, block, 0, b->stream, r);
+            else
+                hipLaunchKernelGGL((kc::batch_row_kernel<8, 1>), grid, block, 0, b->stream, r);
+        }
+        KB_HIP(b, hipGetLastError());
+        b->cur ^= 1;
+        b->steps += nsteps;
+        b->nsamp += (int)ns;
+        return KC_OK;
+    }
     const int T = run_depth(b->T, sample_every);
     if (b->geom_dirty || T != b->geom_T) { // strip numbering depends on T and rows
         const int rc = layout(b, T);

@@ -176,3 +176,49 @@ def test_batch_autotune_keeps_results():
         gb, gn = B.get_fields(k)
         assert np.array_equal(gb, ref[1][k][0]) and np.array_equal(gn, ref[1][k][1])
     B.close()
+
+
+ROWS = [(400, 0.71, 5.0), (64, 1.07, 2.5), (333, 2.0, 0.0), (512, 0.35, 10.0), (5, 1.0, 1.0),
+        (257, 3.0, 1.0)]
+
+
+@pytest.mark.parametrize("law", ["constant", "receptor"])
+def test_single_row_batch_matches_the_single_instance_solver(law):
+    """A batch of single rows (ny = 1, at most 512 cells: the 1-D front
+    experiment's shape) runs in one launch per kb_run; every instance equals
+    the single-instance solver on the same nx x 1 grid: fields bit for bit,
+    time and radii exactly, mass and nutrient to 1e-13."""
+    from paper_1301_5058_amd.batch import Batch
+    from paper_1301_5058_amd.solver import Solver
+    c = workload.FRONT1D
+    descs, fields = [], []
+    for nx, n0, chi in ROWS:
+        h = c["length"] / 400
+        b, n, s = workload.front1d_fields(nx, nx * h, n0)
+        s = (s * np.linspace(0.7, 1.3, nx, dtype=np.float32)[None, :]).astype(np.float32)
+        dt = workload.front1d_dt(nx, nx * h, n0, chi)
+        descs.append(dict(nx=nx, ny=1, h=h, dt=dt, chi=chi, b_thr=0.5 * n0, cx=-0.5, cy=0.0))
+        fields.append((b, n, s))
+    every, blocks = 70, 9  # 70 steps between samples: not a multiple of any launch depth
+    B = Batch(descs, chi_law=law, max_samples=2 * blocks)
+    for k, (b, n, s) in enumerate(fields):
+        B.set_fields(k, b, n, s)
+    B.run(every * 5, every)
+    B.run(every * (blocks - 5), every)  # a second run continues the series
+    series = B.series()
+    out = [B.get_fields(k) for k in range(len(descs))]
+    B.close()
+    for k, d in enumerate(descs):
+        b, n, s = fields[k]
+        S = Solver(d["nx"], 1, h=d["h"], dt=d["dt"], chi=d["chi"], chi_law=law,
+                   b_thr=d["b_thr"], cx=-0.5, cy=0.0)
+        S.set_fields(b, n, s)
+        for i in range(blocks):
+            S.step(every)
+            t, mass, nut, re, ra = S.diagnostics_all()
+            row = series[k, i]
+            assert row[0] == t and row[3] == re and row[4] == ra, (k, i, row, (t, re, ra))
+            np.testing.assert_allclose(row[1:3], [mass, nut], rtol=1e-13, atol=0)
+        gb, gn = S.get_fields()
+        S.close()
+        assert np.array_equal(out[k][0], gb) and np.array_equal(out[k][1], gn), k
