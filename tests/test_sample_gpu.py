@@ -102,3 +102,24 @@ def test_step_sample_rejects_bad_arguments():
     with pytest.raises(ValueError):
         S.step_sample(1, torch.zeros(5, dtype=torch.float32, device="cuda"))
     S.close()
+
+
+def test_step_sample_with_the_reference_kernel():
+    """With the reference kernel selected kc_step_sample is kc_step then
+    kc_diagnostics_device: the same numbers exactly."""
+    outs = []
+    for fused in (False, True):
+        S = _solver(100, 60, "fp32", "rk2", True, (2, 9, 4))
+        S.use_reference_kernel()
+        o = torch.zeros(5, dtype=torch.float64, device="cuda")
+        if fused:
+            S.step_sample(5, o)
+        else:
+            S.step(5)
+            S.diagnostics_device(o)
+        torch.cuda.synchronize()
+        outs.append((o.cpu().numpy(), S.get_fields()))
+        S.close()
+    (a, fa), (b, fb) = outs
+    assert np.array_equal(a, b)
+    assert np.array_equal(fa[0], fb[0]) and np.array_equal(fa[1], fb[1])
