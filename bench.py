@@ -105,10 +105,32 @@ def cpu_baseline(b, n, s, dt, chi, budget_s=15.0):
     oracle.run(b64, n64, s64, 1.0, dt, steps, chi=chi)
     el = time.perf_counter() - t0
     cells = b.size
+    cores = oracle.threads()
+    # the same oracle on one thread, a few steps (about a third of the budget)
+    oracle.set_threads(1)
+    try:
+        t0 = time.perf_counter()
+        oracle.run(b64, n64, s64, 1.0, dt, 1, chi=chi)
+        per1 = time.perf_counter() - t0
+        steps1 = int(max(1, min(200, budget_s / 3 / max(per1, 1e-9))))
+        t0 = time.perf_counter()
+        oracle.run(b64, n64, s64, 1.0, dt, steps1, chi=chi)
+        el1 = time.perf_counter() - t0
+    finally:
+        oracle.set_threads(cores)
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+    except OSError:
+        pass
     return {"value": round(cells * steps / el / 1e9, 5), "unit": "GCell-updates/s",
-            "cores": oracle.threads(), "kind": "oracle",
+            "cores": cores, "kind": "oracle",
             "sample": "FP64 C oracle, %d steps of the same %dx%d fields (%.1f s)"
-                      % (steps, b.shape[1], b.shape[0], el)}
+                      % (steps, b.shape[1], b.shape[0], el),
+            "single_thread": {"value": round(cells * steps1 / el1 / 1e9, 5), "steps": steps1,
+                              "seconds": round(el1, 2)},
+            "host": {"cpu_model": model, "nproc": os.cpu_count()}}
 
 
 def progress(msg):

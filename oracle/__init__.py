@@ -81,6 +81,8 @@ def _load():
         lib.oracle_diag.restype = None
         lib.oracle_threads.argtypes = []
         lib.oracle_threads.restype = ctypes.c_int
+        lib.oracle_set_threads.argtypes = [ctypes.c_int]
+        lib.oracle_set_threads.restype = None
         _lib = lib
     return _lib
 
@@ -174,6 +176,11 @@ def diag(b, n, h, b_thr, cx=None, cy=None, area=False):
 def threads():
     """OpenMP threads the oracle step uses."""
     return int(_load().oracle_threads())
+
+
+def set_threads(n):
+    """Run the following oracle calls on n OpenMP threads (timing only)."""
+    _load().oracle_set_threads(int(n))
 
 
 from .cbar import bstar, cbar, psi  # noqa: E402,F401

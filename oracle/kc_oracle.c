@@ -318,6 +318,19 @@ void oracle_diag(int nx, int ny, double h, const double *b, const double *n,
     *area_radius = h * sqrt(count / 3.14159265358979323846);
 }
 
+/* Threads for the following calls (n >= 1; no effect without OpenMP).  Only the
+ * timing of the oracle depends on it: every cell is computed the same way. */
+void oracle_set_threads(int n)
+{
+#ifdef _OPENMP
+    extern void omp_set_num_threads(int);
+    if (n >= 1)
+        omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* Number of OpenMP threads oracle_step runs with (1 without OpenMP). */
 int oracle_threads(void)
 {
