@@ -3,8 +3,12 @@ the routing between them.
 
 A point is (n0, chi, a): initial nutrient, chemotactic strength (receptor law)
 and agar-noise amplitude.  Its velocity is measured by running the solver on
-a side x side grid from the seeded inoculum and fitting the slope of the
-envelope radius over the window [4 r0, 0.8 side/2] (kb_fit_velocity).  The
+a side x side grid (512^2 by default) from the seeded inoculum and fitting
+the slope of the radius over the fixed window [4 r0, 102.4] cells
+(kb_fit_velocity).  The grid is twice the window's reach so that its walls
+do not change the speed: over this window a 512^2 grid agrees with a 2048^2
+one within the seed-to-seed spread, while a 256^2 grid, whose walls the
+window nearly touches, is up to a fifth slower for slow colonies.  The
 surrogate answers points inside the convex hull of its training inputs; the
 others go to the batched solver.  This module only chooses instances and
 moves arrays; the solver, the fit, the network and the hull test run in
@@ -24,8 +28,11 @@ R0 = 6.0
 SAMPLE_EVERY = 100
 
 
-def window(side, h=1.0):
-    return 4.0 * R0 * h, 0.8 * side * h / 2.0
+WINDOW = (4.0 * R0, 0.8 * 256 / 2.0)  # radii fitted, in cells
+
+
+def window(h=1.0):
+    return WINDOW[0] * h, WINDOW[1] * h
 
 
 def solver_velocities(points, side, steps, seeds=(0,), tune=True, max_batch=1024,
@@ -33,13 +40,14 @@ def solver_velocities(points, side, steps, seeds=(0,), tune=True, max_batch=1024
     """Velocity of every (point, seed) pair: returns (v [m, len(seeds)], npts, gpu_seconds).
 
     gpu_seconds is the device time of the runs and fits (events on the batch
-    stream), not the host-side generation of the initial fields."""
+    stream), not the host-side generation of the initial fields.  The radius
+    window is WINDOW on every grid."""
     points = np.asarray(points, dtype=np.float64)
     m = len(points)
     pairs = [(i, s) for i in range(m) for s in seeds]
     v = np.full((m, len(seeds)), np.nan)
     npts = np.zeros((m, len(seeds)), dtype=np.int32)
-    lo, hi = window(side)
+    lo, hi = window()
     gpu_s = 0.0
     for c0 in range(0, len(pairs), max_batch):
         chunk = pairs[c0:c0 + max_batch]
@@ -143,27 +151,34 @@ def design_grid(per_axis=16):
     return g
 
 
-def run_velocity_map(side=256, steps=8000, per_axis=16, held_out=64, ref_seeds=(101, 102, 103, 104),
-                     query=512, band=256, seed=7):
+def run_velocity_map(side=512, steps=8000, per_axis=16, held_out=64, ref_seeds=(101, 102, 103, 104),
+                     query=512, band=256, seed=7, ref_side_large=2048, train_seeds=(0, 1),
+                     log=None):
     """Train the surrogate on solver velocities, compare it on held-out points
     with the seed-averaged solver (the reference velocities), and time a query
-    map with fallback.
+    map with fallback.  With ref_side_large the held-out references are also
+    taken on that larger grid over the same radius window (no wall within
+    reach), which shows what the training grid's walls do to the velocities.
 
     Returns a dict of the measurements (all velocities by the area radius)."""
     rng = np.random.default_rng(seed)
     out = dict(protocol=dict(side=side, steps=steps, sample_every=SAMPLE_EVERY, radius="area",
-                             window=list(window(side)), box_lo=BOX_LO.tolist(),
+                             window=list(window()), box_lo=BOX_LO.tolist(),
                              box_hi=BOX_HI.tolist()))
-    # 1. training velocities from the batched solver (one seed per point)
+    # 1. training velocities from the batched solver (mean over train_seeds per point)
     X = design_grid(per_axis)
     t0 = time.perf_counter()
-    v, npts, gpu_train = solver_velocities(X, side, steps, seeds=(0,))
-    v = v[:, 0]
+    # the mean over train_seeds agar fields: the per-seed spread (about 1 %) is
+    # noise the network would otherwise fit
+    v, npts, gpu_train = solver_velocities(X, side, steps, seeds=tuple(train_seeds))
+    v = np.nanmean(v, axis=1)
+    if log:
+        log("training velocities: %d points" % len(X))
     host_train = time.perf_counter() - t0
     ok = np.isfinite(v)
-    out["train"] = dict(points=int(len(X)), finite=int(ok.sum()), solver_gpu_s=round(gpu_train, 3),
-                        wall_s=round(host_train, 2),
-                        solver_pts_per_s=round(len(X) / gpu_train, 2))
+    out["train"] = dict(points=int(len(X)), seeds=len(train_seeds), finite=int(ok.sum()),
+                        solver_gpu_s=round(gpu_train, 3), wall_s=round(host_train, 2),
+                        solver_pts_per_s=round(len(X) * len(train_seeds) / gpu_train, 2))
     # 2. surrogate training on the GPU
     vm = VelocityMap()
     st = torch.cuda.current_stream()
@@ -177,6 +192,8 @@ def run_velocity_map(side=256, steps=8000, per_axis=16, held_out=64, ref_seeds=(
     # 3. held-out reference: random interior points, solver averaged over seeds
     H = BOX_LO + (BOX_HI - BOX_LO) * rng.uniform(0.02, 0.98, (held_out, 3))
     vr, _, gpu_ref = solver_velocities(H, side, steps, seeds=tuple(ref_seeds))
+    if log:
+        log("held-out references on %d^2" % side)
     vref = np.nanmean(vr, axis=1)
     spread = np.nanstd(vr, axis=1) / vref
     pred = vm.S.predict(H.astype(np.float32)).astype(np.float64)
@@ -195,6 +212,25 @@ def run_velocity_map(side=256, steps=8000, per_axis=16, held_out=64, ref_seeds=(
                            scaled_cbar_rel_err_median=float(np.median(rel_cb)),
                            scaled_cbar_rel_err_p95=float(np.quantile(rel_cb, 0.95)),
                            cbar_scale=scale, ref_gpu_s=round(gpu_ref, 3))
+    if ref_side_large:
+        vl, _, gpu_l = solver_velocities(H, ref_side_large, steps, seeds=tuple(ref_seeds),
+                                         max_batch=64)
+        vlarge = np.nanmean(vl, axis=1)
+        if log:
+            log("held-out references on %d^2" % ref_side_large)
+        rel_l = np.abs(pred - vlarge) / vlarge
+        wall = (vref - vlarge) / vlarge
+        out["held_out_large"] = dict(side=int(ref_side_large), points=int(held_out),
+                                     seeds=len(ref_seeds),
+                                     ref_seed_spread_median=float(np.median(
+                                         np.nanstd(vl, axis=1) / vlarge)),
+                                     training_grid_vs_large_median=float(np.median(wall)),
+                                     training_grid_vs_large_max_abs=float(np.max(np.abs(wall))),
+                                     surrogate_rel_err_median=float(np.median(rel_l)),
+                                     surrogate_rel_err_p95=float(np.quantile(rel_l, 0.95)),
+                                     surrogate_rel_err_max=float(np.max(rel_l)),
+                                     surrogate_within_2pct=float(np.mean(rel_l <= 0.02)),
+                                     ref_gpu_s=round(gpu_l, 3))
     # 4. query map: query x query (n0, chi) at a = 0.3 inside the box, plus a band outside
     n0q, chq = np.meshgrid(np.linspace(BOX_LO[0], BOX_HI[0], query),
                            np.linspace(BOX_LO[1], BOX_HI[1], query), indexing="ij")
@@ -213,3 +249,32 @@ def run_velocity_map(side=256, steps=8000, per_axis=16, held_out=64, ref_seeds=(
                         speedup=round((len(allq) / total_s) / out["train"]["solver_pts_per_s"], 1))
     vm.S.close()
     return out
+
+
+def main(argv=None):
+    import argparse
+    import json
+    import os
+    import sys
+    ap = argparse.ArgumentParser(description="velocity surrogate: training, held-out check, query map")
+    ap.add_argument("--ref-side-large", type=int, default=2048,
+                    help="also take the held-out references on this larger grid (0: no)")
+    ap.add_argument("--json", default=None)
+    a = ap.parse_args(argv)
+    here = os.path.dirname(os.path.abspath(__file__))
+    os.environ.setdefault("KC_AUTOTUNE_CACHE", os.path.join(here, "tuning", "gfx950.jsonl"))
+    def log(msg):
+        print("[velocity map] " + msg, file=sys.stderr, flush=True)
+
+    out = run_velocity_map(ref_side_large=a.ref_side_large, log=log)
+    txt = json.dumps(out, indent=1)
+    print(txt, flush=True)
+    if a.json:
+        with open(a.json, "w") as f:
+            f.write(txt)
+    return 0
+
+
+if __name__ == "__main__":
+    import sys
+    sys.exit(main())
