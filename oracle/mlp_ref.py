@@ -13,6 +13,11 @@ difference can check.
 
 Parameter vector layout (8641): W1[64][3] b1[64] W2[64][64] b2[64] W3[64][64]
 b3[64] W4[64] b4.
+
+adam_step is one step of Adam (Kingma and Ba, "Adam: a method for stochastic
+optimization", ICLR 2015, Algorithm 1) in float64: exponential moving
+averages of the gradient and of its square, both divided by their bias
+corrections, and a step of lr times their ratio.
 """
 import numpy as np
 from scipy.special import erf
@@ -107,3 +112,19 @@ def loss_and_grad(params, X, y, in_shift=(0, 0, 0), in_scale=(1, 1, 1), out_shif
     g["b1"] = dz1.sum(0)
     g["W1"] = dz1.T @ C["x"]
     return loss, pack(g)
+
+
+def adam_step(params, grad, m, v, t, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    """One Adam step at step number t >= 1 (the first step is t = 1).
+
+    m <- beta1 m + (1 - beta1) g,  v <- beta2 v + (1 - beta2) g^2,
+    params <- params - lr mhat / (sqrt(vhat) + eps) with the bias-corrected
+    mhat = m / (1 - beta1^t) and vhat = v / (1 - beta2^t).
+    Returns new (params, m, v) as float64 arrays."""
+    g = np.asarray(grad, dtype=np.float64)
+    m = beta1 * np.asarray(m, dtype=np.float64) + (1.0 - beta1) * g
+    v = beta2 * np.asarray(v, dtype=np.float64) + (1.0 - beta2) * g * g
+    mhat = m / (1.0 - beta1 ** t)
+    vhat = v / (1.0 - beta2 ** t)
+    p = np.asarray(params, dtype=np.float64) - lr * mhat / (np.sqrt(vhat) + eps)
+    return p, m, v

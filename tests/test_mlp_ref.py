@@ -73,3 +73,44 @@ def test_bf16_emulation_stays_close_to_the_plain_network():
 def test_pack_unpack_roundtrip():
     p, *_ = _setup()
     assert np.array_equal(mlp_ref.pack(mlp_ref.unpack(p)), p)
+
+
+def test_adam_constant_gradient_moves_lr_per_step():
+    # With a constant gradient g the bias-corrected moments are exactly g and
+    # g^2 at every step, so each step moves lr g / (|g| + eps): after k steps
+    # the closed form p0 - k lr g / (|g| + eps).
+    rng = np.random.default_rng(4)
+    p0 = rng.uniform(-1, 1, 50)
+    g = rng.uniform(-2, 2, 50) * 10.0 ** rng.integers(-6, 2, 50)
+    p, m, v = p0.copy(), np.zeros(50), np.zeros(50)
+    lr = 3e-3
+    for t in range(1, 26):
+        p, m, v = mlp_ref.adam_step(p, g, m, v, t, lr)
+        want = p0 - t * lr * g / (np.abs(g) + 1e-8)
+        np.testing.assert_allclose(p, want, rtol=0, atol=1e-13 * t)
+
+
+def test_adam_matches_torch_adam_on_a_gradient_sequence():
+    # the library routine torch.optim.Adam (float64, CPU) on the same gradients
+    import torch
+    rng = np.random.default_rng(5)
+    p0 = rng.uniform(-1, 1, 200)
+    grads = [rng.normal(0, 1, 200) * 10.0 ** rng.integers(-9, 1, 200) for _ in range(40)]
+    w = torch.tensor(p0.copy(), dtype=torch.float64, requires_grad=True)
+    opt = torch.optim.Adam([w], lr=2e-3, betas=(0.9, 0.999), eps=1e-8, foreach=False)
+    p, m, v = p0.copy(), np.zeros(200), np.zeros(200)
+    for t, g in enumerate(grads, start=1):
+        opt.zero_grad()
+        w.grad = torch.tensor(g, dtype=torch.float64)
+        opt.step()
+        p, m, v = mlp_ref.adam_step(p, g, m, v, t, 2e-3)
+        np.testing.assert_allclose(p, w.detach().numpy(), rtol=0, atol=1e-14)
+
+
+def test_adam_first_step_is_lr_times_the_gradient_sign():
+    # first step from zero moments: mhat = g, vhat = g^2
+    g = np.array([3.0, -1e-3, 0.0, 2e-12])
+    p, m, v = mlp_ref.adam_step(np.zeros(4), g, np.zeros(4), np.zeros(4), 1, 0.5)
+    np.testing.assert_allclose(p, -0.5 * g / (np.abs(g) + 1e-8), rtol=1e-15, atol=0)
+    np.testing.assert_allclose(m, 0.1 * g, rtol=1e-14)
+    np.testing.assert_allclose(v, 0.001 * g * g, rtol=1e-13)
