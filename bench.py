@@ -1,16 +1,19 @@
 """Benchmark: explicit chemotaxis step on a 4096 x 4096 FP32 grid, one MI355X.
 
-    python bench.py [--gpus 1] [--steps 50000] [--warmup 1000] [--no-cpu-baseline]
+    python bench.py [--gpus 1] [--steps 500] [--warmup 10] [--no-cpu-baseline]
                     [--no-extras] [--copy-ref-mib M]
 
 Workload (seeded, synthetic; the paper's set-up of Sec. 3): uniform nutrient
 n0 = 0.5, Gaussian inoculum b_max = 0.7 / radius 6 cells at the centre, agar
 field sigma = 1 + 0.5 U[-1, 1] per cell (seed 0), chi = 1 (receptor law),
 theta = kappa = D_n = 1, h = 1, dt = 0.2 h^2 / max(D_n, max sigma n b).
-A step is one time step of the whole grid; every 100 steps the diagnostics
-(mass, nutrient, envelope radius) are sampled into a device series, as a run
-that tracks the colony envelope does.  Inputs are resident in HBM before the
-timed region.  Prints one JSON line.
+One benchmark step is one pass of the whole hot path: 100 time steps of the
+grid followed by the diagnostics (mass, nutrient, envelope and area radius,
+folded into the last step launch) sampled into a device series, as a run that
+tracks the colony envelope does; the defaults time 500 such steps (50,000 time
+steps) after 10 (1,000 time steps) of warm-up.  The value is cell-updates
+(cells x time steps) per second.  Inputs are resident in HBM before the timed
+region.  Prints one JSON line.
 
 The line also carries, under "extras", the other workloads of the solver:
 the FP64 variant, chi = 0, the two-stage Runge-Kutta integrator (FP32 and
@@ -50,13 +53,21 @@ BYTES_PER_CELL_LAUNCH_NOISE = {"fp32": 16, "fp64": 32}
 OPS_PER_NOISE_DRAW = 13
 # per-step agar noise of the 4096^2 workload: sigma = 1 + 0.5 Delta, redrawn every step
 NOISE_4096 = {"sigma0": 1.0, "amp": 0.5, "seed": 2013}
-SAMPLE_EVERY = 100
+SAMPLE_EVERY = 100  # time steps per benchmark step (one diagnostics sample each)
 T_START = time.perf_counter()
+# published MI355X FP32 vector peak (packed FMA) and the non-packed half of it
+FP32_PEAK_TFLOPS = 157.3
+FP32_NONPACKED_TFLOPS = 78.6
+# floating-point operations per cell-update (FMA = 2): 33 VALU operations of which
+# 6 are FMAs, 2 compares, 2 selects and 1 reciprocal; counted as flops: 55 with
+# the FMAs doubled and the selects and compares included (the survey's count)
+FLOPS_PER_CELL_UPDATE = 55
 METRIC = "GCell-updates/s & % HBM peak (4096^2 FP32); velocity-map pts/s at <=2% err"
 STEP_SOURCES = ("paper_1301_5058_amd/csrc/kc_step.hip", "paper_1301_5058_amd/csrc/kc_step_kernels.h",
                 "paper_1301_5058_amd/csrc/kc_stream_f32_euler.hip",
                 "paper_1301_5058_amd/csrc/kc_stream.h", "paper_1301_5058_amd/csrc/kc_device.h")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_stream_4096_fp32_traffic.txt")
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "step_stream_4096_fp32_counters.txt")
 # shipped autotune database (written by paper_1301_5058_amd/tune_db.py on an MI355X);
 # grids without an entry are timed on the spot
 os.environ.setdefault("KC_AUTOTUNE_CACHE",
@@ -87,6 +98,29 @@ def measured_traffic(tsteps, rows, prefetch):
         return None
     try:
         return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def measured_counters(tsteps, rows, prefetch):
+    """VALU counters of the step kernel from the committed PMC summary (issued
+    VALU instructions per useful cell-update, VALU busy fraction), or None when
+    the summary is missing or was taken for another configuration or older
+    kernel sources."""
+    try:
+        txt = open(COUNTERS_FILE).read()
+    except OSError:
+        return None
+    kv = dict(re.findall(r"^(\w+)\s*=\s*(\S+)", txt, flags=re.M))
+    if kv.get("kernel_sources_sha256_16") != kernel_hash():
+        return None
+    if (int(kv.get("tsteps", -1)), int(kv.get("rows", -1)), int(kv.get("prefetch", -1))) != \
+            (tsteps, rows, prefetch):
+        return None
+    try:
+        return {"valu_issued_per_update": float(kv["valu_issued_per_update"]),
+                "valu_busy": float(kv["valu_busy"]),
+                "source": os.path.relpath(COUNTERS_FILE, ROOT)}
     except (KeyError, ValueError):
         return None
 
@@ -171,7 +205,8 @@ def roofline(precision, cells, tsteps, launch_ms, ops_per_update=OPS_PER_CELL_UP
 
 
 def timed_run(S, stream, steps, series=None):
-    """K steps with diagnostics every SAMPLE_EVERY steps; returns elapsed ms."""
+    """`steps` time steps with diagnostics every SAMPLE_EVERY steps; returns
+    elapsed ms."""
     import torch
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -219,29 +254,34 @@ def run(args):
     progress("autotuned 4096^2 fp32: T=%d rows=%d prefetch=%d (%.1f GCell/s)"
              % (tsteps, rows, pf, tuned))
 
-    nsamp = args.steps // SAMPLE_EVERY + 2
-    series = torch.zeros((nsamp, 5), dtype=torch.float64, device=dev)
-    left = args.warmup
-    while left > 0:  # warmup (same code path)
-        k = min(SAMPLE_EVERY, left)
-        S.step(k)
-        left -= k
+    time_steps = args.steps * SAMPLE_EVERY
+    series = torch.zeros((args.steps + 1, 5), dtype=torch.float64, device=dev)
+    if args.warmup:  # the same code path
+        timed_run(S, stream, args.warmup * SAMPLE_EVERY, series)
     torch.cuda.synchronize()
 
     t_wall = time.perf_counter()
-    total_ms = timed_run(S, stream, args.steps, series)
+    total_ms = timed_run(S, stream, time_steps, series)
     wall = time.perf_counter() - t_wall
     cells = nx * ny
-    value = cells * args.steps / (total_ms / 1e3) / 1e9
-    last = series[(args.steps + SAMPLE_EVERY - 1) // SAMPLE_EVERY - 1].cpu().numpy()
+    value = cells * time_steps / (total_ms / 1e3) / 1e9
+    last = series[args.steps - 1].cpu().numpy()
 
-    progress("timed %d steps: %.1f GCell/s" % (args.steps, value))
+    progress("timed %d steps (%d time steps): %.1f GCell/s" % (args.steps, time_steps, value))
     launch_ms = launch_probe(S, stream)
     main_rl, other_rl = roofline("fp32", cells, tsteps, launch_ms)
     main_rl["traffic"] = measured_traffic(tsteps, rows, pf)
     main_rl["kernel"] = "step_stream<float,T=%d,PF=%d>" % (tsteps, pf)
     main_rl["launch_us"] = round(launch_ms * 1e3, 3)
     main_rl["other_bound"] = other_rl
+    # the same launch priced in flops: 55 per update against the published
+    # FP32 peak (which counts packed FMAs, not used here) and its non-packed half
+    tflops = FLOPS_PER_CELL_UPDATE * cells * tsteps / (launch_ms / 1e3) / 1e12
+    main_rl["flop_view"] = {"flops_per_update": FLOPS_PER_CELL_UPDATE,
+                            "achieved_tflops": round(tflops, 2),
+                            "frac_of_157_3": round(tflops / FP32_PEAK_TFLOPS, 4),
+                            "frac_of_nonpacked_78_6": round(tflops / FP32_NONPACKED_TFLOPS, 4)}
+    main_rl["counters"] = measured_counters(tsteps, rows, pf)
     S.close()
 
     out = {
@@ -252,13 +292,15 @@ def run(args):
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(total_ms / args.steps, 6),
+        "time_steps_per_step": SAMPLE_EVERY,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "single instance 4096x4096 FP32, n0=0.5, sigma amplitude 0.5, "
-                               "chi=1 receptor law, forward Euler, diagnostics every 100 steps",
+                               "chi=1 receptor law, forward Euler; one step = 100 time steps "
+                               "+ fused diagnostics",
                    "nx": nx, "ny": ny, "dt": dt, "chi": chi, "tsteps": tsteps, "rows": rows,
                    "prefetch": pf, "autotune_gcell_s": round(tuned, 1)},
         "roofline": main_rl,
@@ -466,8 +508,9 @@ def front1d_speeds():
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50000)
-    ap.add_argument("--warmup", type=int, default=1000)
+    ap.add_argument("--steps", type=int, default=500,
+                    help="benchmark steps of %d time steps + diagnostics each" % SAMPLE_EVERY)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--quick-tune", action="store_true")

@@ -26,7 +26,10 @@
  * flags (device-scope release / acquire).  Every item waited on was handed out
  * earlier, to a running wavefront, so the launch always drains.  Each wait is
  * also bounded (kb_set_spin_limit): a wait that exceeds the bound stops the
- * launch and kb_run reports KC_EHIP.  On gfx950 a device-scope release or
+ * launch (every other waiting wavefront sees the stop and leaves too) and
+ * kb_run reports KC_EHIP; strips that had finished a block have then already
+ * overwritten a level, so the fields of every instance must be set again
+ * (kb_run and kb_get_fields return KC_ESTATE until kb_set_fields).  On gfx950 a device-scope release or
  * acquire writes back or invalidates the issuing XCD's L2, once per item, so
  * the persistent mode is slower than per-block launches at every batch size
  * measured; the autotuner always selects per-block launches.  A batch whose

@@ -51,7 +51,7 @@ extern "C" {
 #define KC_OK 0
 #define KC_EINVAL -1     /* null pointer, nx or ny < 1, h <= 0, dt <= 0, negative rate, bad enum, size overflow */
 #define KC_ENONFINITE -2 /* NaN / Inf or negative value in b0, n0 or sigma                               */
-#define KC_EUNSTABLE -3  /* dt > h^2 / (4 max(D_n, max sigma n b)) on the fields given to kc_set_fields  */
+#define KC_EUNSTABLE -3  /* dt above the explicit bound of the fields given to kc_set_fields (kc_check_step) */
 #define KC_ESTATE -4     /* step / diagnostics / get before kc_set_fields                                */
 #define KC_ENOMEM -5     /* device or host allocation failed                                             */
 #define KC_EHIP -6       /* no usable device, or a HIP runtime error                                     */
@@ -114,9 +114,9 @@ int kc_create(const kc_grid *g, double h, double dt, const kc_params *p, void *h
 /* Copy initial fields b0 (bacteria), n0 (nutrient) and sigma (agar field,
  * eq. CoefCrsDif) into the context; mem says where the three arrays live.
  * Rejects NaN / Inf / negative entries (KC_ENONFINITE) and a dt above the
- * explicit stability bound for these fields (KC_EUNSTABLE); on failure the
- * context keeps its previous state.  Resets the step count to p->step0.
- * With KC_NOISE_PER_STEP sigma is not used (may be NULL) and the bound takes
+ * explicit bounds of kc_check_step for these fields (KC_EUNSTABLE); on failure
+ * the context keeps its previous state.  Resets the step count to p->step0.
+ * With KC_NOISE_PER_STEP sigma is not used (may be NULL) and the bounds take
  * the largest sigma the noise can draw, sigma0 (1 + noise_amp). */
 int kc_set_fields(kc_ctx *ctx, const void *b0, const void *n0, const void *sigma, int mem);
 
@@ -164,6 +164,26 @@ double kc_suggest_dt(double h, double D_n, double max_sigma_n_b);
  * *max_sigma_n_b (may be NULL) receives max sigma n b over the cells. */
 int kc_check_fields(int32_t nx, int32_t ny, int precision, const void *b0, const void *n0,
                     const void *sigma, double *max_sigma_n_b);
+
+/* Host-side stability check of dense host arrays for a step dt on cells of
+ * width h with the rates, sensitivity and noise of *p (no device work; sigma
+ * may be NULL with KC_NOISE_PER_STEP, which takes sigma0 (1 + noise_amp)
+ * everywhere).  With D = sigma n b, two bounds apply (eqs. eqnadim / eqbadim
+ * discretised as in the header comment):
+ *   diffusion:   dt <= h^2 / (4 max(D_n, max D)), the explicit limit of both
+ *                fields (it keeps n >= 0 and n <= max n0);
+ *   positivity:  dt <= h^2 / max_P [ sum_Q (D_P + D_Q) / 2
+ *                  + chi sigma_P n_P b_P chihat(n_P) sum_{Q: n_Q > n_P} (n_Q - n_P) ],
+ *                Q over the existing neighbours of P: b_P loses at most this
+ *                fraction of itself per step through its faces (diffusion and
+ *                the donor-cell chemotactic flux toward higher nutrient), so b
+ *                stays >= 0.
+ * Returns KC_OK, KC_EINVAL (bad arguments), KC_ENONFINITE (NaN / Inf /
+ * negative entries) or KC_EUNSTABLE; *dt_max (may be NULL) receives the
+ * largest dt both bounds allow for these fields.  The bounds hold for the
+ * given fields; a run whose fields sharpen later may need a smaller step. */
+int kc_check_step(int32_t nx, int32_t ny, int precision, const void *b0, const void *n0,
+                  const void *sigma, double h, double dt, const kc_params *p, double *dt_max);
 
 /* Kernel configuration: tsteps = time steps fused into one launch (1..8; 1..3
  * with KC_RK2, whose steps take two levels of the fused kernel each),

@@ -120,7 +120,10 @@ __global__ __launch_bounds__(256) void batch_kernel(BatchArgs a)
                     const unsigned *f = &a.flags[I.strip0 + qy * I.nsx + qx];
                     while (__hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
                            (unsigned)tau) {
-                        if (++polls > a.spin_limit) {
+                        // give up when the bound is exceeded or another wave has stopped
+                        if (++polls > a.spin_limit ||
+                            __hip_atomic_load(a.abort_flag, __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT)) {
                             __hip_atomic_store(a.abort_flag, 1u, __ATOMIC_RELAXED,
                                                __HIP_MEMORY_SCOPE_AGENT);
                             return;
@@ -150,7 +153,7 @@ __global__ __launch_bounds__(256) void batch_kernel(BatchArgs a)
         DiagAcc acc{0.0, 0.0, -1.0, 0.0};
         {
             const int sx = j % I.nsx, sy = j / I.nsx;
-            if (strip_interior<float, T>(sa, sx, sy))
+            if (strip_inside<float, T>(sa, sx))
                 stream_strip<float, T, LAW, PF, false>(sa, sx, sy);
             else
                 stream_strip<float, T, LAW, PF, true>(sa, sx, sy);
@@ -167,7 +170,9 @@ __global__ __launch_bounds__(256) void batch_kernel(BatchArgs a)
                 long long polls = 0;
                 while (__hip_atomic_load(&a.fin[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
                        (unsigned)s) {
-                    if (++polls > a.spin_limit) {
+                    if (++polls > a.spin_limit ||
+                        __hip_atomic_load(a.abort_flag, __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_AGENT)) {
                         __hip_atomic_store(a.abort_flag, 1u, __ATOMIC_RELAXED,
                                            __HIP_MEMORY_SCOPE_AGENT);
                         return;
@@ -723,9 +728,10 @@ int kb_set_fields(kb_batch *b, int32_t k, const float *b0, const float *n0, cons
         return bfail(b, KC_EINVAL, "bad arguments to kb_set_fields (instance %d)", k);
     const kb_instance &I = b->inst[k];
     const size_t cells = (size_t)I.nx * I.ny;
-    double mx = 0.0;
+    double mx = 0.0, rate = 0.0;
     if (mem == KC_MEM_HOST) {
-        const int rc = kc_check_fields(I.nx, I.ny, KC_FP32, b0, n0, sigma, &mx);
+        const int rc = kc::host_check<float>(I.nx, I.ny, b0, n0, sigma, 1.0, I.chi, b->law, &mx,
+                                             &rate);
         if (rc != KC_OK)
             return bfail(b, rc, "instance %d: input fields rejected: %s", k, kc_strerror(rc));
     } else {
@@ -733,25 +739,26 @@ int kb_set_fields(kb_batch *b, int32_t k, const float *b0, const float *n0, cons
         if (b->dcheck)
             (void)hipFree(b->dcheck);
         b->dcheck = nullptr;
-        KB_HIP(b, hipMalloc((void **)&b->dcheck, 2 * (size_t)cp * sizeof(double)));
-        if (ensure_pinned(b, 2 * (size_t)cp) != KC_OK)
+        KB_HIP(b, hipMalloc((void **)&b->dcheck, 4 * (size_t)cp * sizeof(double)));
+        if (ensure_pinned(b, 4 * (size_t)cp) != KC_OK)
             return KC_ENOMEM;
-        KB_HIP(b, kc::launch_check<float>(b0, n0, sigma, cells, b->dcheck, b->stream));
-        KB_HIP(b, hipMemcpyAsync(b->hpin, b->dcheck, 2 * cp * sizeof(double),
+        KB_HIP(b, kc::launch_check<float>(b0, n0, sigma, I.nx, I.ny, 1.0, I.chi, b->law, b->dcheck,
+                                          b->stream));
+        KB_HIP(b, hipMemcpyAsync(b->hpin, b->dcheck, 4 * cp * sizeof(double),
                                  hipMemcpyDeviceToHost, b->stream));
         KB_HIP(b, hipStreamSynchronize(b->stream));
         double nbad = 0;
         for (int i = 0; i < cp; ++i) {
-            nbad += b->hpin[2 * i];
-            mx = b->hpin[2 * i + 1] > mx ? b->hpin[2 * i + 1] : mx;
+            nbad += b->hpin[4 * i];
+            mx = b->hpin[4 * i + 1] > mx ? b->hpin[4 * i + 1] : mx;
+            rate = b->hpin[4 * i + 2] > rate ? b->hpin[4 * i + 2] : rate;
         }
         if (nbad > 0)
             return bfail(b, KC_ENONFINITE, "instance %d: %.0f NaN/Inf/negative entries", k, nbad);
     }
-    const double dmax = I.D_n > mx ? I.D_n : mx;
-    if (dmax > 0 && I.dt > I.h * I.h / (4.0 * dmax))
-        return bfail(b, KC_EUNSTABLE, "instance %d: dt = %g exceeds h^2/(4 max D) = %g", k, I.dt,
-                     I.h * I.h / (4.0 * dmax));
+    char msg[256];
+    if (kc::stability(I.h, I.dt, I.D_n, mx, rate, msg, sizeof msg) != KC_OK)
+        return bfail(b, KC_EUNSTABLE, "instance %d: %s", k, msg);
     const BInst &H = b->hinst[k];
     const hipMemcpyKind kind = mem == KC_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
     const size_t sp = (size_t)I.nx * sizeof(float), dp = (size_t)H.pitch * sizeof(float);
@@ -879,10 +886,15 @@ int kb_run(kb_batch *b, int64_t nsteps, int32_t sample_every)
         KB_HIP(b, hipMemcpyAsync(&abort_h, a.abort_flag, sizeof(unsigned),
                                  hipMemcpyDeviceToHost, b->stream));
         KB_HIP(b, hipStreamSynchronize(b->stream));
-        if (abort_h)
+        if (abort_h) {
+            // strips that finished a block have already overwritten a level: the
+            // fields now mix different times and must be set again
+            std::fill(b->has_fields.begin(), b->has_fields.end(), (char)0);
             return bfail(b, KC_EHIP,
-                         "persistent batch launch stopped: a wait exceeded %lld polls",
+                         "persistent batch launch stopped: a wait exceeded %lld polls; the "
+                         "fields must be set again",
                          b->spin_limit);
+        }
     }
     b->cur = (int)((b->cur + blocks) & 1);
     b->steps += nsteps;

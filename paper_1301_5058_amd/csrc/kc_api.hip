@@ -240,8 +240,13 @@ template <typename R> int step_impl(kc_ctx *c, int64_t nsteps, double *dev_out5 
     return KC_OK;
 }
 
-// s null: sigma = 1 everywhere
-template <typename R> int check_host(int nx, int ny, const R *b, const R *n, const R *s, double *mx)
+} // namespace
+
+namespace kc {
+
+template <typename R>
+int host_check(int nx, int ny, const R *b, const R *n, const R *s, double sscale, double chi,
+               int law, double *max_snb, double *max_rate)
 {
     const size_t cells = (size_t)nx * (size_t)ny;
     double m = 0.0;
@@ -249,14 +254,69 @@ template <typename R> int check_host(int nx, int ny, const R *b, const R *n, con
         const double bv = b[i], nv = n[i], sv = s ? s[i] : 1.0;
         if (!(isfinite(bv) && isfinite(nv) && isfinite(sv)) || bv < 0 || nv < 0 || sv < 0)
             return KC_ENONFINITE;
-        const double v = sv * nv * bv;
+        const double v = sv * sscale * nv * bv;
         if (v > m)
             m = v;
     }
-    if (mx)
-        *mx = m;
+    double rate = 0.0;
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+            const size_t i = (size_t)y * nx + x;
+            const double nP = n[i];
+            const double DP = (s ? (double)s[i] : 1.0) * sscale * nP * (double)b[i];
+            double dsum = 0.0, up = 0.0;
+            const int dx[4] = {1, -1, 0, 0}, dy[4] = {0, 0, 1, -1};
+            for (int q = 0; q < 4; ++q) {
+                const int xq = x + dx[q], yq = y + dy[q];
+                if (xq < 0 || xq >= nx || yq < 0 || yq >= ny)
+                    continue;
+                const size_t j = (size_t)yq * nx + xq;
+                const double nQ = n[j];
+                dsum += 0.5 * (DP + (s ? (double)s[j] : 1.0) * sscale * nQ * (double)b[j]);
+                if (nQ > nP)
+                    up += nQ - nP;
+            }
+            const double ch = law == KC_CHI_RECEPTOR ? 1.0 / ((1.0 + nP) * (1.0 + nP)) : 1.0;
+            const double r = dsum + chi * DP * ch * up;
+            if (r > rate)
+                rate = r;
+        }
+    if (max_snb)
+        *max_snb = m;
+    if (max_rate)
+        *max_rate = rate;
     return KC_OK;
 }
+
+template int host_check<float>(int, int, const float *, const float *, const float *, double,
+                               double, int, double *, double *);
+template int host_check<double>(int, int, const double *, const double *, const double *, double,
+                                double, int, double *, double *);
+
+int stability(double h, double dt, double D_n, double max_snb, double max_rate, char *msg,
+              size_t msg_n)
+{
+    // diffusive bound of both fields, h^2 / (4 max(D_n, sigma n b)), and the
+    // positivity bound of the donor-cell b-step, h^2 / max outflow rate
+    const double dmax = D_n > max_snb ? D_n : max_snb;
+    if (dmax > 0 && dt > h * h / (4.0 * dmax)) {
+        snprintf(msg, msg_n, "dt = %g exceeds h^2/(4 max(D_n, sigma n b)) = %g", dt,
+                 h * h / (4.0 * dmax));
+        return KC_EUNSTABLE;
+    }
+    if (max_rate > 0 && dt > h * h / max_rate) {
+        snprintf(msg, msg_n,
+                 "dt = %g exceeds the positivity bound h^2 / max(sum of face diffusivities + "
+                 "chemotactic outflow) = %g",
+                 dt, h * h / max_rate);
+        return KC_EUNSTABLE;
+    }
+    return KC_OK;
+}
+
+} // namespace kc
+
+namespace {
 
 bool sizes_ok(int nx, int ny)
 {
@@ -371,12 +431,47 @@ int kc_check_fields(int32_t nx, int32_t ny, int precision, const void *b0, const
     if (!b0 || !n0 || !sigma || !sizes_ok(nx, ny))
         return KC_EINVAL;
     if (precision == KC_FP32)
-        return check_host<float>(nx, ny, (const float *)b0, (const float *)n0,
-                                 (const float *)sigma, max_sigma_n_b);
+        return kc::host_check<float>(nx, ny, (const float *)b0, (const float *)n0,
+                                     (const float *)sigma, 1.0, 0.0, KC_CHI_CONSTANT,
+                                     max_sigma_n_b, nullptr);
     if (precision == KC_FP64)
-        return check_host<double>(nx, ny, (const double *)b0, (const double *)n0,
-                                  (const double *)sigma, max_sigma_n_b);
+        return kc::host_check<double>(nx, ny, (const double *)b0, (const double *)n0,
+                                      (const double *)sigma, 1.0, 0.0, KC_CHI_CONSTANT,
+                                      max_sigma_n_b, nullptr);
     return KC_EINVAL;
+}
+
+int kc_check_step(int32_t nx, int32_t ny, int precision, const void *b0, const void *n0,
+                  const void *sigma, double h, double dt, const kc_params *p, double *dt_max)
+{
+    if (dt_max)
+        *dt_max = 0.0;
+    if (!b0 || !n0 || !sizes_ok(nx, ny) || !(h > 0) || !isfinite(h) || !(dt > 0) ||
+        !isfinite(dt) || check_params(p) != KC_OK || (precision != KC_FP32 && precision != KC_FP64))
+        return KC_EINVAL;
+    const bool noise = p->noise == KC_NOISE_PER_STEP;
+    if (!noise && !sigma)
+        return KC_EINVAL;
+    const double sscale = noise ? p->sigma0 * (1.0 + p->noise_amp) : 1.0;
+    if (noise)
+        sigma = nullptr;
+    double mx = 0.0, rate = 0.0;
+    const int rc = precision == KC_FP32
+                       ? kc::host_check<float>(nx, ny, (const float *)b0, (const float *)n0,
+                                               (const float *)sigma, sscale, p->chi, p->chi_law,
+                                               &mx, &rate)
+                       : kc::host_check<double>(nx, ny, (const double *)b0, (const double *)n0,
+                                                (const double *)sigma, sscale, p->chi, p->chi_law,
+                                                &mx, &rate);
+    if (rc != KC_OK)
+        return rc;
+    double lim = 4.0 * (p->D_n > mx ? p->D_n : mx);
+    if (rate > lim)
+        lim = rate;
+    if (dt_max)
+        *dt_max = lim > 0 ? h * h / lim : INFINITY;
+    char msg[256];
+    return kc::stability(h, dt, p->D_n, mx, rate, msg, sizeof msg);
 }
 
 int kc_create(const kc_grid *g, double h, double dt, const kc_params *p, void *hip_stream,
@@ -437,7 +532,7 @@ int kc_create(const kc_grid *g, double h, double dt, const kc_params *p, void *h
         const int np = kc::diag_parts(c->ny);
         const size_t cells = (size_t)c->nx * c->ny;
         const int cp = kc::check_parts(cells);
-        const size_t nparts = (size_t)(4 * np > 2 * cp ? 4 * np : 2 * cp);
+        const size_t nparts = (size_t)(4 * np > 4 * cp ? 4 * np : 4 * cp);
         e = hipMalloc((void **)&c->dparts, (nparts + 5) * sizeof(double));
         if (e != hipSuccess)
             rc = e == hipErrorOutOfMemory ? KC_ENOMEM : KC_EHIP;
@@ -445,7 +540,7 @@ int kc_create(const kc_grid *g, double h, double dt, const kc_params *p, void *h
             c->dout5 = c->dparts + nparts;
     }
     if (rc == KC_OK) {
-        e = hipHostMalloc((void **)&c->hout, (2 * kc::check_parts((size_t)c->nx * c->ny) + 5) *
+        e = hipHostMalloc((void **)&c->hout, (4 * kc::check_parts((size_t)c->nx * c->ny) + 5) *
                                                  sizeof(double),
                           hipHostMallocDefault);
         if (e != hipSuccess)
@@ -486,32 +581,35 @@ int kc_set_fields(kc_ctx *c, const void *b0, const void *n0, const void *sigma, 
     if (mem != KC_MEM_HOST && mem != KC_MEM_DEVICE)
         return fail(c, KC_EINVAL, "bad memory kind %d", mem);
     const size_t cells = (size_t)c->nx * c->ny;
-    // with per-step noise the check takes sigma = 1 (a null sigma) and the
-    // stability bound is scaled by the largest sigma the noise can draw,
-    // sigma0 (1 + amp)
+    // with per-step noise the check takes sigma = 1 (a null sigma) scaled by the
+    // largest sigma the noise can draw, sigma0 (1 + amp)
+    const double sscale = noise ? c->p.sigma0 * (1.0 + c->p.noise_amp) : 1.0;
     if (noise)
         sigma = nullptr;
-    double mx = 0.0;
+    double mx = 0.0, rate = 0.0;
     int rc = KC_OK;
     if (mem == KC_MEM_HOST) {
         rc = c->p.precision == KC_FP32
-                 ? check_host<float>(c->nx, c->ny, (const float *)b0, (const float *)n0,
-                                     (const float *)sigma, &mx)
-                 : check_host<double>(c->nx, c->ny, (const double *)b0, (const double *)n0,
-                                      (const double *)sigma, &mx);
+                 ? kc::host_check<float>(c->nx, c->ny, (const float *)b0, (const float *)n0,
+                                         (const float *)sigma, sscale, c->p.chi, c->p.chi_law, &mx,
+                                         &rate)
+                 : kc::host_check<double>(c->nx, c->ny, (const double *)b0, (const double *)n0,
+                                          (const double *)sigma, sscale, c->p.chi, c->p.chi_law,
+                                          &mx, &rate);
         if (rc != KC_OK)
             rc = fail(c, rc, "input fields rejected: %s", kc_strerror(rc));
     } else {
         const int cp = kc::check_parts(cells);
         hipError_t e = c->p.precision == KC_FP32
                            ? kc::launch_check<float>((const float *)b0, (const float *)n0,
-                                                     (const float *)sigma, cells, c->dparts,
-                                                     c->stream)
+                                                     (const float *)sigma, c->nx, c->ny, sscale,
+                                                     c->p.chi, c->p.chi_law, c->dparts, c->stream)
                            : kc::launch_check<double>((const double *)b0, (const double *)n0,
-                                                      (const double *)sigma, cells, c->dparts,
+                                                      (const double *)sigma, c->nx, c->ny, sscale,
+                                                      c->p.chi, c->p.chi_law, c->dparts,
                                                       c->stream);
         if (e == hipSuccess)
-            e = hipMemcpyAsync(c->hout, c->dparts, 2 * cp * sizeof(double),
+            e = hipMemcpyAsync(c->hout, c->dparts, 4 * cp * sizeof(double),
                                hipMemcpyDeviceToHost, c->stream);
         if (e == hipSuccess)
             e = hipStreamSynchronize(c->stream);
@@ -520,9 +618,9 @@ int kc_set_fields(kc_ctx *c, const void *b0, const void *n0, const void *sigma, 
         } else {
             double nbad = 0.0;
             for (int i = 0; i < cp; ++i) {
-                nbad += c->hout[2 * i];
-                if (c->hout[2 * i + 1] > mx)
-                    mx = c->hout[2 * i + 1];
+                nbad += c->hout[4 * i];
+                mx = c->hout[4 * i + 1] > mx ? c->hout[4 * i + 1] : mx;
+                rate = c->hout[4 * i + 2] > rate ? c->hout[4 * i + 2] : rate;
             }
             if (nbad > 0)
                 rc = fail(c, KC_ENONFINITE, "input fields rejected: %.0f NaN/Inf/negative entries",
@@ -531,12 +629,9 @@ int kc_set_fields(kc_ctx *c, const void *b0, const void *n0, const void *sigma, 
     }
     if (rc != KC_OK)
         return rc;
-    if (noise)
-        mx *= c->p.sigma0 * (1.0 + c->p.noise_amp);
-    const double dmax = c->p.D_n > mx ? c->p.D_n : mx;
-    if (dmax > 0 && c->dt > c->h * c->h / (4.0 * dmax))
-        return fail(c, KC_EUNSTABLE, "dt = %g exceeds h^2/(4 max(D_n, sigma n b)) = %g", c->dt,
-                    c->h * c->h / (4.0 * dmax));
+    char msg[256];
+    if (kc::stability(c->h, c->dt, c->p.D_n, mx, rate, msg, sizeof msg) != KC_OK)
+        return fail(c, KC_EUNSTABLE, "%s", msg);
 
     const hipMemcpyKind kind = mem == KC_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
     const size_t spitch = (size_t)c->nx * c->esz, dpitch = (size_t)c->pitch * c->esz;

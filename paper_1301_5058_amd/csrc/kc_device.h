@@ -64,7 +64,10 @@ __device__ __forceinline__ void face(R bP, R nP, R DP, R XP, R bQ, R nQ, R DQ, R
 {
     const R dn = nQ - nP;
     const R db = bQ - bP;
-    const R xu = (nQ > nP) ? XP : XQ;
+    // donor: dn > 0 exactly when nQ > nP (gradual underflow keeps the sign of a
+    // non-zero difference; the kernels keep denormals), and it lets the
+    // neighbour's nQ arrive through a DPP operand of the subtraction alone
+    const R xu = (dn > R(0)) ? XP : XQ;
     const R g = fmaR(-xu, dn, (DP + DQ) * db);
     gb = valid ? g : R(0);
     gn = valid ? dn : R(0);

@@ -9,8 +9,9 @@
 //   {t, h^2 sum b, h^2 sum n, h sqrt(max d^2), h sqrt(count / pi)}; it also
 //   folds the per-strip partials that a fused step launch writes.
 // check_partial: input validation of dense device arrays: per block, the
-//   count of NaN / Inf / negative entries and the max of sigma n b (sigma taken
-//   as 1 when its pointer is null).
+//   count of NaN / Inf / negative entries, the max of sigma n b and the max of
+//   the donor-cell outflow rate (cell_rate; sigma taken as 1 when its pointer
+//   is null, and scaled by sscale).
 #include "kc_internal.h"
 
 namespace kc {
@@ -137,11 +138,45 @@ hipError_t launch_diag(const R *b, const R *n, int nx, int ny, int pitch, double
 // ---------------------------------------------------------------------------
 static constexpr int kCheckBlocks = 1024;
 
+// Per-cell outflow rate of the donor-cell step (times h^2), the quantity whose
+// product with dt / h^2 must stay <= 1 for b' >= 0:
+//   sum over the existing neighbours Q of (D_P + D_Q) / 2
+//   + chi sigma_P n_P b_P chihat(n_P) sum over Q with n_Q > n_P of (n_Q - n_P),
+// D = sigma n b (eq. eqbadim; the chemotactic flux leaves P through every face
+// toward higher nutrient with the donor coefficient X_P = sigma n b^2 chihat).
 template <typename R>
-__global__ __launch_bounds__(256) void check_partial(const R *b, const R *n, const R *sg,
-                                                      size_t cells, double *parts)
+__device__ __forceinline__ double cell_rate(const R *b, const R *n, const R *sg, int nx, int ny,
+                                            int x, int y, double sscale, double chi, int law)
 {
-    double nbad = 0.0, mx = 0.0, unused = 0.0, unused2 = 0.0;
+    const size_t i = (size_t)y * nx + x;
+    const double sP = (sg ? (double)sg[i] : 1.0) * sscale;
+    const double nP = (double)n[i], bP = (double)b[i];
+    const double DP = sP * nP * bP;
+    double dsum = 0.0, up = 0.0;
+    const int dx[4] = {1, -1, 0, 0}, dy[4] = {0, 0, 1, -1};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int xq = x + dx[q], yq = y + dy[q];
+        if (xq < 0 || xq >= nx || yq < 0 || yq >= ny)
+            continue;
+        const size_t j = (size_t)yq * nx + xq;
+        const double nQ = (double)n[j];
+        const double DQ = (sg ? (double)sg[j] : 1.0) * sscale * nQ * (double)b[j];
+        dsum += 0.5 * (DP + DQ);
+        if (nQ > nP)
+            up += nQ - nP;
+    }
+    const double ch = law == 0 ? 1.0 / ((1.0 + nP) * (1.0 + nP)) : 1.0;
+    return dsum + chi * DP * ch * up;
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void check_partial(const R *b, const R *n, const R *sg, int nx,
+                                                      int ny, double sscale, double chi, int law,
+                                                      double *parts)
+{
+    double nbad = 0.0, mx = 0.0, rate = 0.0, unused = 0.0;
+    const size_t cells = (size_t)nx * ny;
     const size_t stride = (size_t)gridDim.x * 256;
     for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < cells; i += stride) {
         const R bv = b[i], nv = n[i], sv = sg ? sg[i] : R(1);
@@ -150,12 +185,24 @@ __global__ __launch_bounds__(256) void check_partial(const R *b, const R *n, con
         if (!ok)
             nbad += 1.0;
         else
-            mx = fmax(mx, (double)sv * (double)nv * (double)bv);
+            mx = fmax(mx, (double)sv * sscale * (double)nv * (double)bv);
     }
-    block_reduce4(nbad, unused, mx, unused2);
+    if (nbad == 0.0) // neighbours may be non-finite otherwise; the block reports them
+        for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < cells; i += stride)
+            rate = fmax(rate, cell_rate<R>(b, n, sg, nx, ny, (int)(i % nx), (int)(i / nx), sscale,
+                                           chi, law));
+    // block_reduce4 sums its first, second and fourth values and takes the max of
+    // the third: the two maxima go through the max slot one after the other
+    double m1 = mx;
+    block_reduce4(nbad, unused, m1, unused);
+    __syncthreads();
+    double z0 = 0.0, z1 = 0.0, z3 = 0.0, m2 = rate;
+    block_reduce4(z0, z1, m2, z3);
     if (threadIdx.x == 0) {
-        parts[2 * blockIdx.x + 0] = nbad;
-        parts[2 * blockIdx.x + 1] = mx;
+        parts[4 * blockIdx.x + 0] = nbad;
+        parts[4 * blockIdx.x + 1] = m1;
+        parts[4 * blockIdx.x + 2] = m2;
+        parts[4 * blockIdx.x + 3] = 0.0;
     }
 }
 
@@ -166,11 +213,12 @@ int check_parts(size_t cells)
 }
 
 template <typename R>
-hipError_t launch_check(const R *b, const R *n, const R *sg, size_t cells, double *parts,
-                        hipStream_t s)
+hipError_t launch_check(const R *b, const R *n, const R *sg, int nx, int ny, double sscale,
+                        double chi, int law, double *parts, hipStream_t s)
 {
-    hipLaunchKernelGGL((check_partial<R>), dim3(check_parts(cells)), dim3(256), 0, s, b, n, sg,
-                       cells, parts);
+    const size_t cells = (size_t)nx * ny;
+    hipLaunchKernelGGL((check_partial<R>), dim3(check_parts(cells)), dim3(256), 0, s, b, n, sg, nx,
+                       ny, sscale, chi, law, parts);
     return hipGetLastError();
 }
 
@@ -179,9 +227,9 @@ template hipError_t launch_diag<float>(const float *, const float *, int, int, i
 template hipError_t launch_diag<double>(const double *, const double *, int, int, int, double,
                                         double, double, double, double, double *, double *,
                                         hipStream_t);
-template hipError_t launch_check<float>(const float *, const float *, const float *, size_t,
-                                        double *, hipStream_t);
-template hipError_t launch_check<double>(const double *, const double *, const double *, size_t,
-                                         double *, hipStream_t);
+template hipError_t launch_check<float>(const float *, const float *, const float *, int, int,
+                                        double, double, int, double *, hipStream_t);
+template hipError_t launch_check<double>(const double *, const double *, const double *, int, int,
+                                         double, double, int, double *, hipStream_t);
 
 } // namespace kc

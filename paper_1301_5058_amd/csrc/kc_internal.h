@@ -122,12 +122,28 @@ hipError_t launch_diag(const R *b, const R *n, int nx, int ny, int pitch, double
 hipError_t launch_diag_fold(const double *parts, int nparts, double h, double t, double *out5,
                             hipStream_t s);
 
-// Input check of dense device arrays: block k writes parts[2k] = number of
-// NaN / Inf / negative entries it saw and parts[2k+1] = its max of sigma n b,
-// for k < check_parts(cells); a null sg counts as sigma = 1 everywhere.
+// Input check of dense device arrays [ny][nx]: block k writes
+// parts[4k .. 4k + 3] = {number of NaN / Inf / negative entries it saw, its max
+// of sigma n b, its max of the donor-cell outflow rate (see host_check), 0} for
+// k < check_parts(nx * ny); a null sg counts as sigma = 1 everywhere, and
+// sigma is multiplied by sscale.
 int check_parts(size_t cells);
 template <typename R>
-hipError_t launch_check(const R *b, const R *n, const R *sg, size_t cells, double *parts,
-                        hipStream_t s);
+hipError_t launch_check(const R *b, const R *n, const R *sg, int nx, int ny, double sscale,
+                        double chi, int law, double *parts, hipStream_t s);
+
+// The same check of dense host arrays: KC_OK or KC_ENONFINITE; *max_snb =
+// max sigma n b and *max_rate = max over cells P of
+//   sum_Q (D_P + D_Q) / 2 + chi sigma_P n_P b_P chihat(n_P) sum_{Q: n_Q > n_P} (n_Q - n_P)
+// (D = sigma n b, Q over the existing neighbours), the outflow rate of b at P
+// times h^2: the forward-Euler step keeps b >= 0 when dt max_rate <= h^2.
+template <typename R>
+int host_check(int nx, int ny, const R *b, const R *n, const R *s, double sscale, double chi,
+               int law, double *max_snb, double *max_rate);
+
+// Stability of dt for fields with max sigma n b = max_snb and outflow rate
+// max_rate: KC_OK, or KC_EUNSTABLE with a message in msg.
+int stability(double h, double dt, double D_n, double max_snb, double max_rate, char *msg,
+              size_t msg_n);
 
 } // namespace kc

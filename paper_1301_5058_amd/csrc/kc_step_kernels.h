@@ -52,10 +52,13 @@ __global__ __launch_bounds__(256) void step_stream(StepArgs<R> a)
     sa.cx = a.cx;
     sa.cy = a.cy;
     const int sx = strip % a.nsx, sy = strip / a.nsx;
-    if (strip_interior<R, T>(sa, sx, sy))
+    constexpr int VEC = StreamShape<R>::VEC;
+    if (strip_inside<R, T>(sa, sx))
         stream_strip<R, T, LAW, PF, false, RK, NOISE>(sa, sx, sy);
-    else
+    else if (!NOISE || a.nx % VEC == 0)
         stream_strip<R, T, LAW, PF, true, RK, NOISE>(sa, sx, sy);
+    else // noise on a grid whose width is not a multiple of VEC: per-cell draws at the edges
+        stream_strip<R, T, LAW, PF, true, RK, NOISE, true>(sa, sx, sy);
     if (a.parts) {
         // fold the cells this strip stored into its partials (no separate pass
         // over the fields; a wave-uniform test on a kernel argument)

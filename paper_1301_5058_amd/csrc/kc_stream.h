@@ -11,10 +11,24 @@
 // launch: read b, n, sigma once, write b', n' once, plus halo re-reads that
 // mostly hit L2.
 //
+// No-flux walls by reflection: cells outside the grid are ghost cells holding
+// the values of their mirror images (row -1 mirrors row 0, row -2 row 1, ...,
+// column nx mirrors column nx - 1, ...; the even extension of period 2 nx, 2 ny).
+// A face between a cell and its mirror then carries exactly +0 (equal values
+// on both sides), which is what a masked boundary face contributes, and a
+// ghost cell's update is bit for bit its mirror's: the face fluxes on the
+// mirrored side are exact negations (x - y = -(y - x), the donor choice and
+// the fused multiply-add are symmetric under the reflection).  So the kernel
+// needs no face masks and no boundary-specific arithmetic; its cells are the
+// same bits as the masked one-step reference kernel's.  A strip whose cells
+// all lie in the grid (EDGE = false) loads 16-byte vectors; an edge strip
+// loads cell by cell from the mirrored columns (the rows are mirrored in both).
+//
 // With NOISE the agar field is redrawn at every time step (noise_half_sigma,
 // kc_device.h): each level computes sigma of its incoming row for the step it
 // advances instead of loading it (the two Runge-Kutta levels of a step share
-// the step's field, passed along as before).
+// the step's field, passed along as before).  A ghost cell draws its mirror's
+// sigma.
 //
 // With RK, each time step is two levels of the two-stage Runge-Kutta method
 // u' = (u + E(E(u))) / 2 (E = one forward-Euler step): an even level hands the
@@ -27,9 +41,7 @@
 // row whose only purpose is the face flux below the first needed row.  The test
 // is wave-uniform, so skipped rows cost a scalar branch, and a group of PF rows
 // on which every level is active (the steady state between the first T - 1 + T
-// and the last rows) runs a straight-line body without it.  A strip whose halo
-// window lies strictly inside the domain (CHECK = false) needs no boundary-face
-// masks and no load predicates; edge strips run the checked code.
+// and the last rows) runs a straight-line body without it.
 //
 // strip_diag reads back the cells a strip has just stored (each lane its own
 // addresses, so program order makes the stores visible) and folds them into a
@@ -74,20 +86,77 @@ struct DiagAcc {
     double sb, sn, m2, cnt;
 };
 
-// True when every face and load of strip (sx, sy) lies inside the domain.
+// Index r reflected into [0, n): the even extension of period 2 n (row -1 is
+// row 0, row n is row n - 1).  Uniform or per lane; a few steps at most.
+__device__ __forceinline__ int mirror_index(int r, int n)
+{
+    while (r < 0 || r >= n)
+        r = r < 0 ? -1 - r : 2 * n - 1 - r;
+    return r;
+}
+
+// Buffer resource of one row of a field (base, size in bytes): loads and
+// stores through it take the row base in scalar registers and a 32-bit byte
+// offset per lane, so no per-lane 64-bit address arithmetic is issued; an
+// offset past the row reads 0 and writes nothing.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const void *row, int nbytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(row), (short)0, nbytes,
+                                             0x00020000);
+}
+
+template <typename V> __device__ __forceinline__ V buf_load(__amdgpu_buffer_rsrc_t r, uint32_t off);
+template <> __device__ __forceinline__ float buf_load<float>(__amdgpu_buffer_rsrc_t r, uint32_t off)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+template <> __device__ __forceinline__ double buf_load<double>(__amdgpu_buffer_rsrc_t r, uint32_t off)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+template <typename V> __device__ __forceinline__ V buf_load16(__amdgpu_buffer_rsrc_t r, uint32_t off)
+{
+    static_assert(sizeof(V) == 16, "16-byte vector");
+    return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+}
+template <typename V>
+__device__ __forceinline__ void buf_store16(V v, __amdgpu_buffer_rsrc_t r, uint32_t off)
+{
+    static_assert(sizeof(V) == 16, "16-byte vector");
+    typedef unsigned u4 __attribute__((ext_vector_type(4)));
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4, v), r, off, 0, 0);
+}
+
+// (a & m) | (b & ~m) bit for bit, m all ones or all zeros.
+__device__ __forceinline__ float select_bits(uint32_t m, float a, float b)
+{
+    return __uint_as_float((__float_as_uint(a) & m) | (__float_as_uint(b) & ~m));
+}
+__device__ __forceinline__ double select_bits(uint32_t m, double a, double b)
+{
+    const uint64_t mm = ((uint64_t)m << 32) | m;
+    return __longlong_as_double((int64_t)(((uint64_t)__double_as_longlong(a) & mm) |
+                                          ((uint64_t)__double_as_longlong(b) & ~mm)));
+}
+
+// The same for 0 <= r < 2 n (one reflection at the far wall, no branch).
+__device__ __forceinline__ int mirror_high(int r, int n) { return r >= n ? 2 * n - 1 - r : r; }
+
+// True when every cell of strip (sx, sy) lies inside the columns of the grid
+// (the vectorised loads need no reflection).
 template <typename R, int T>
-__device__ __forceinline__ bool strip_interior(const StripArgs<R> &a, int sx, int sy)
+__device__ __forceinline__ bool strip_inside(const StripArgs<R> &a, int sx)
 {
     constexpr int VEC = StreamShape<R>::VEC;
     constexpr int HX = Halo<T, VEC>::HX;
     constexpr int OW = Halo<T, VEC>::OW;
     constexpr int WC = Halo<T, VEC>::WC;
     const int xl = sx * OW - HX;
-    const int y0 = sy * a.rows, y1 = min(y0 + a.rows, a.ny);
-    return xl >= 0 && xl + WC <= a.nx - 1 && y0 >= T && y1 + T <= a.ny;
+    return xl >= 0 && xl + WC <= a.nx;
 }
 
-template <typename R, int T, int LAW, int PF, bool CHECK, bool RK = false, bool NOISE = false>
+template <typename R, int T, int LAW, int PF, bool EDGE, bool RK = false, bool NOISE = false,
+          bool GEN = false>
 __device__ __forceinline__ void stream_strip(const StripArgs<R> &a, int sx, int sy)
 {
     static_assert(!RK || T % 2 == 0, "a two-stage Runge-Kutta block has an even level count");
@@ -101,13 +170,21 @@ __device__ __forceinline__ void stream_strip(const StripArgs<R> &a, int sx, int 
     const int x0 = sx * OW - HX + lane * VEC; // first column of this lane
     const int y0 = sy * a.rows;
     const int y1 = min(y0 + a.rows, a.ny);
-    const int rs = max(y0 - T, 0); // first input row
-    const int re = y1 + T;         // one past the last input row needed
+    const int rs = y0 - T; // first input row (rows outside the grid are mirrored)
+    const int re = y1 + T; // one past the last input row needed
     const bool lane_out = (lane * VEC >= HX) && (lane * VEC < WC - HX) && (x0 < a.nx);
-    bool ve[VEC]; // east face of cell k is interior
+
+    // Edge strips: the mirrored column of each of the lane's cells.  When nx is
+    // a multiple of VEC (GEN = false) the reflections map every aligned block of
+    // VEC cells onto an aligned block, forward or reversed, so a lane's noise is
+    // one generator call for that block; otherwise (GEN) each cell draws its own.
+    int xm[VEC];
 #pragma unroll
     for (int k = 0; k < VEC; ++k)
-        ve[k] = !CHECK || ((x0 + k >= 0) && (x0 + k + 1 < a.nx));
+        xm[k] = EDGE ? mirror_index(x0 + k, a.nx) : x0 + k;
+    const bool nrev = EDGE && xm[VEC - 1] < xm[0]; // the block is reversed
+    const int nbx = nrev ? xm[VEC - 1] : xm[0];     // its first column
+    const uint32_t rmask = nrev ? 0xffffffffu : 0u; // bit mask of the reversal
 
     // level state: centre row of level L and the face inflow G(S,P) below it;
     // with RK, the second level of each step also holds the step's input u of
@@ -121,29 +198,70 @@ __device__ __forceinline__ void stream_strip(const StripArgs<R> &a, int sx, int 
             cb[L][k] = cn[L][k] = cD[L][k] = cX[L][k] = cs[L][k] = fb[L][k] = fn[L][k] =
                 cub[L][k] = cun[L][k] = R(0);
 
-    // Prefetch ring: slot (row - rs) % PF.  Loads are unconditional, from
-    // addresses clamped into the array: a row past the last input row or a
-    // column outside [0, pitch) yields some in-bounds value that only ever
-    // meets a zero (masked) face or a skipped level, never a stored cell.
-    // (A conditional load would make the compiler merge the two arms through
-    // a register copy, which waits for the load it was meant to hide.)
+    // Prefetch ring: slot (row - rs) % PF.  Rows are reflected into the grid
+    // (rows past re are loaded and never used); interior strips load one
+    // 16-byte vector per field, edge strips one cell at a time from the
+    // mirrored columns.
+    // In the steady state (FULL groups) every row is >= 0 and below 2 ny, so one
+    // branch-free reflection suffices; the lead-in and tail groups reflect in
+    // general.
     vec_t pb[PF], pn[PF], ps[PF];
-    const int last_row = min(re, a.ny) - 1;
-    const int xc = min(max(x0, 0), a.pitch - VEC);
-    auto load_row = [&](int row, vec_t &vb, vec_t &vn, vec_t &vs) __attribute__((always_inline)) {
-        const size_t p = (size_t)min(row, last_row) * a.pitch + xc;
-        vb = *reinterpret_cast<const vec_t *>(a.b_in + p);
-        vn = *reinterpret_cast<const vec_t *>(a.n_in + p);
-        if constexpr (!NOISE)
-            vs = *reinterpret_cast<const vec_t *>(a.sg + p);
+    auto mrow = [&](int row, auto full_tag) __attribute__((always_inline)) {
+        if constexpr (decltype(full_tag)::value)
+            return mirror_high(row, a.ny);
         else
-            vs = vec_t{};
+            return mirror_index(row, a.ny);
+    };
+    auto load_row = [&](int row, vec_t &vb, vec_t &vn, vec_t &vs, auto full_tag)
+                        __attribute__((always_inline)) {
+        // the row (uniform) through a buffer resource, the lane's byte offset
+        const size_t base = (size_t)mrow(row, full_tag) * a.pitch;
+        const int nbytes = a.pitch * (int)sizeof(R);
+        const __amdgpu_buffer_rsrc_t rb = row_rsrc(a.b_in + base, nbytes);
+        const __amdgpu_buffer_rsrc_t rn = row_rsrc(a.n_in + base, nbytes);
+        if constexpr (!EDGE) {
+            const uint32_t o = (uint32_t)x0 * (uint32_t)sizeof(R);
+            vb = buf_load16<vec_t>(rb, o);
+            vn = buf_load16<vec_t>(rn, o);
+            if constexpr (!NOISE)
+                vs = buf_load16<vec_t>(row_rsrc(a.sg + base, nbytes), o);
+            else
+                vs = vec_t{};
+        } else {
+#pragma unroll
+            for (int k = 0; k < VEC; ++k) {
+                const uint32_t o = (uint32_t)xm[k] * (uint32_t)sizeof(R);
+                vb[k] = buf_load<R>(rb, o);
+                vn[k] = buf_load<R>(rn, o);
+                vs[k] = NOISE ? R(0) : buf_load<R>(row_rsrc(a.sg + base, nbytes), o);
+            }
+        }
+    };
+    // sigma / 2 of the lane's cells in row `row` at step ds after the launch's
+    // first (the mirror images' for ghost cells)
+    auto draw = [&](int ds, int row, R *out, auto full_tag) __attribute__((always_inline)) {
+        const int yr = mrow(row, full_tag);
+        if (!EDGE) {
+            noise_half_sigma<R, VEC>(a.z, ds, x0, yr, out);
+        } else if (!GEN) {
+            R t[VEC];
+            noise_half_sigma<R, VEC>(a.z, ds, nbx, yr, t);
+            // cell k takes word VEC - 1 - k of a reversed block: one bitwise
+            // select per 32 bits (v_bfi_b32), not a dynamic index
+#pragma unroll
+            for (int k = 0; k < VEC; ++k)
+                out[k] = select_bits(rmask, t[VEC - 1 - k], t[k]);
+        } else {
+#pragma unroll
+            for (int k = 0; k < VEC; ++k)
+                out[k] = noise_half_sigma1<R>(a.z, ds, xm[k], yr);
+        }
     };
     // time step (after the launch's first) that level L advances
     auto level_step = [](int L) { return RK ? L / 2 : L; };
 #pragma unroll
     for (int u = 0; u < PF; ++u)
-        load_row(rs + u, pb[u], pn[u], ps[u]);
+        load_row(rs + u, pb[u], pn[u], ps[u], BoolTag<false>());
 
     // One group of PF rows.  With FULL every level is active on every row of
     // the group (the steady state), so the body is one straight-line block.
@@ -163,8 +281,8 @@ __device__ __forceinline__ void stream_strip(const StripArgs<R> &a, int sx, int 
                 iub[k] = iun[k] = R(0);
             }
             if (NOISE) // sigma of the incoming row at the first level's step
-                noise_half_sigma<R, VEC>(a.z, level_step(0), x0, row, is);
-            load_row(row + PF, pb[u], pn[u], ps[u]);
+                draw(level_step(0), row, is, full_tag);
+            load_row(row + PF, pb[u], pn[u], ps[u], full_tag);
 #pragma unroll
             for (int k = 0; k < VEC; ++k)
                 coef<R, LAW>(is[k], in[k], ib[k], a.c.chi2, iD[k], iX[k]);
@@ -192,21 +310,20 @@ __device__ __forceinline__ void stream_strip(const StripArgs<R> &a, int sx, int 
                     }
                     continue;
                 }
-                const bool vv = !CHECK || ((y >= 0) && (y + 1 < a.ny));
                 R gvb[VEC], gvn[VEC], geb[VEC], gen[VEC];
 #pragma unroll
                 for (int k = 0; k < VEC; ++k)
-                    face<R>(cb[L][k], cn[L][k], cD[L][k], cX[L][k], ib[k], in[k], iD[k], iX[k], vv,
+                    face<R>(cb[L][k], cn[L][k], cD[L][k], cX[L][k], ib[k], in[k], iD[k], iX[k], true,
                             gvb[k], gvn[k]);
 #pragma unroll
                 for (int k = 0; k + 1 < VEC; ++k)
                     face<R>(cb[L][k], cn[L][k], cD[L][k], cX[L][k], cb[L][k + 1], cn[L][k + 1],
-                            cD[L][k + 1], cX[L][k + 1], ve[k], geb[k], gen[k]);
+                            cD[L][k + 1], cX[L][k + 1], true, geb[k], gen[k]);
                 {
                     const R eb = from_next(cb[L][0]), en = from_next(cn[L][0]);
                     const R eD = from_next(cD[L][0]), eX = from_next(cX[L][0]);
                     face<R>(cb[L][VEC - 1], cn[L][VEC - 1], cD[L][VEC - 1], cX[L][VEC - 1], eb, en,
-                            eD, eX, ve[VEC - 1], geb[VEC - 1], gen[VEC - 1]);
+                            eD, eX, true, geb[VEC - 1], gen[VEC - 1]);
                 }
                 const R wb = from_prev(geb[VEC - 1]), wn = from_prev(gen[VEC - 1]);
                 R ob[VEC], on[VEC], os[VEC];
@@ -248,7 +365,7 @@ __device__ __forceinline__ void stream_strip(const StripArgs<R> &a, int sx, int 
                 if (L + 1 < T) {
                     if (NOISE && level_step(L + 1) != level_step(L)) {
                         // the next level advances a later step: fresh sigma of row y
-                        noise_half_sigma<R, VEC>(a.z, level_step(L + 1), x0, y, os);
+                        draw(level_step(L + 1), y, os, full_tag);
                     }
 #pragma unroll
                     for (int k = 0; k < VEC; ++k) {
@@ -264,9 +381,11 @@ __device__ __forceinline__ void stream_strip(const StripArgs<R> &a, int sx, int 
                         vb[k] = ob[k];
                         vn[k] = on[k];
                     }
-                    const size_t p = (size_t)y * a.pitch + x0;
-                    *reinterpret_cast<vec_t *>(a.b_out + p) = vb;
-                    *reinterpret_cast<vec_t *>(a.n_out + p) = vn;
+                    const size_t rowp = (size_t)y * a.pitch;
+                    const int nbytes = a.pitch * (int)sizeof(R);
+                    const uint32_t o = (uint32_t)x0 * (uint32_t)sizeof(R);
+                    buf_store16<vec_t>(vb, row_rsrc(a.b_out + rowp, nbytes), o);
+                    buf_store16<vec_t>(vn, row_rsrc(a.n_out + rowp, nbytes), o);
                 }
             }
         }
@@ -274,12 +393,16 @@ __device__ __forceinline__ void stream_strip(const StripArgs<R> &a, int sx, int 
 
     // every level is active on rows [y0 + T - 1, re): lead-in groups, the
     // steady state, then the tail (three loops, so that the steady loop
-    // carries its state in the same registers from one trip to the next)
+    // carries its state in the same registers from one trip to the next).  The
+    // steady rows, the rows they load ahead and those they draw noise for lie
+    // in [0, ny + T + PF): below 2 ny when ny >= T + PF; smaller grids run every
+    // group as a tail group.
     const int full_lo = y0 + T - 1;
+    const bool steady_ok = a.ny >= T + PF;
     int r0 = rs;
     for (; r0 < re && r0 < full_lo; r0 += PF)
         group(r0, BoolTag<false>());
-    for (; r0 + PF <= re; r0 += PF)
+    for (; steady_ok && r0 + PF <= re; r0 += PF)
         group(r0, BoolTag<true>());
     for (; r0 < re; r0 += PF)
         group(r0, BoolTag<false>());

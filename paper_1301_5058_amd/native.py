@@ -61,6 +61,8 @@ _SIGS = {
     "kc_suggest_dt": (c_double, [c_double, c_double, c_double]),
     "kc_check_fields": (c_int32, [c_int32, c_int32, c_int32, c_void_p, c_void_p, c_void_p,
                                   P_double]),
+    "kc_check_step": (c_int32, [c_int32, c_int32, c_int32, c_void_p, c_void_p, c_void_p, c_double,
+                                c_double, ctypes.POINTER(KcParams), P_double]),
     "kc_set_tuning": (c_int32, [c_void_p, c_int32, c_int32, c_int32]),
     "kc_get_tuning": (c_int32, [c_void_p, ctypes.POINTER(c_int32), ctypes.POINTER(c_int32),
                                 ctypes.POINTER(c_int32)]),

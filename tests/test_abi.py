@@ -178,3 +178,97 @@ def test_batch_null_handles():
     assert L.kb_series(None, None, None, 0) == N.KC_EINVAL
     assert L.kb_set_spin_limit(None, 5) == N.KC_EINVAL
     assert L.kb_last_error(None) == b"null batch"
+
+
+def _check_step(b, n, s, h, dt, **kw):
+    L = N.lib()
+    p = N.default_params()
+    for k, v in kw.items():
+        setattr(p, k, v)
+    b, n = np.ascontiguousarray(b, np.float32), np.ascontiguousarray(n, np.float32)
+    sp = None if s is None else np.ascontiguousarray(s, np.float32)
+    dmax = ctypes.c_double()
+    rc = L.kc_check_step(b.shape[1], b.shape[0], N.KC_FP32, b.ctypes.data, n.ctypes.data,
+                         None if sp is None else sp.ctypes.data, h, dt, ctypes.byref(p),
+                         ctypes.byref(dmax))
+    return rc, dmax.value
+
+
+def _outflow_bound(b, n, s, chi, receptor, D_n=1.0):
+    """The largest dt of the two documented bounds, by a direct numpy loop."""
+    ny, nx = b.shape
+    D = s * n * b
+    rate = 0.0
+    for y in range(ny):
+        for x in range(nx):
+            dsum = up = 0.0
+            for xq, yq in ((x + 1, y), (x - 1, y), (x, y + 1), (x, y - 1)):
+                if 0 <= xq < nx and 0 <= yq < ny:
+                    dsum += 0.5 * (D[y, x] + D[yq, xq])
+                    up += max(n[yq, xq] - n[y, x], 0.0)
+            ch = 1.0 / (1.0 + n[y, x]) ** 2 if receptor else 1.0
+            rate = max(rate, dsum + chi * D[y, x] * ch * up)
+    return 1.0 / max(4.0 * max(D_n, D.max()), rate)
+
+
+def _chemotactic_front(nx=16, ny=12):
+    # b = 0.5 everywhere, nutrient 0.1 on the left half and 1.0 on the right:
+    # the cells left of the jump send their bacteria up the nutrient step
+    b = np.full((ny, nx), 0.5)
+    n = np.full((ny, nx), 0.1)
+    n[:, nx // 2:] = 1.0
+    s = np.ones((ny, nx))
+    return b, n, s
+
+
+def test_stability_check_counts_the_chemotactic_outflow():
+    import oracle
+    b, n, s = _chemotactic_front()
+    chi, dt = 200.0, 0.2
+    # the diffusive bound alone accepts dt = 0.2: max sigma n b = 0.5 <= D_n = 1
+    mx = ctypes.c_double()
+    L = N.lib()
+    bf, nf, sf = (np.ascontiguousarray(a, np.float32) for a in (b, n, s))
+    assert L.kc_check_fields(16, 12, N.KC_FP32, bf.ctypes.data, nf.ctypes.data, sf.ctypes.data,
+                             ctypes.byref(mx)) == N.KC_OK
+    assert dt <= 1.0 / (4.0 * max(1.0, mx.value))
+    # ... but one step of that size drives b negative next to the jump (oracle)
+    ob, _ = oracle.step(bf, nf, sf, 1.0, dt, chi=chi, chi_law=N.KC_CHI_CONSTANT)
+    assert ob.min() < 0
+    rc, dmax = _check_step(b, n, s, 1.0, dt, chi=chi, chi_law=N.KC_CHI_CONSTANT)
+    assert rc == N.KC_EUNSTABLE
+    # the bound it reports: left of the jump, the face diffusivities
+    # 3 x 0.05 + (0.05 + 0.5) / 2 plus chi sigma n b (1.0 - 0.1) up the jump
+    assert dmax == pytest.approx(1.0 / (0.425 + chi * 0.05 * 0.9), rel=1e-6)
+    assert dmax == pytest.approx(_outflow_bound(b, n, s, chi, False), rel=1e-6)
+    # a step of that size keeps b >= 0 on these fields (the bound is for the
+    # fields it is given: the pile-up it causes at the jump needs a smaller
+    # step afterwards), and the check accepts it
+    rc2, _ = _check_step(b, n, s, 1.0, dmax, chi=chi, chi_law=N.KC_CHI_CONSTANT)
+    assert rc2 == N.KC_OK
+    ob, _ = oracle.step(bf, nf, sf, 1.0, dmax, chi=chi, chi_law=N.KC_CHI_CONSTANT)
+    assert ob.min() >= 0
+    # the receptor law divides the chemotactic coefficient by (1 + n)^2
+    _, dmax_r = _check_step(b, n, s, 1.0, dt, chi=chi, chi_law=N.KC_CHI_RECEPTOR)
+    assert dmax_r == pytest.approx(_outflow_bound(b, n, s, chi, True), rel=1e-6)
+    assert dmax_r > dmax
+    # no chemotaxis: only the diffusive bound, 1 / (4 max(D_n, sigma n b))
+    rc0, dmax0 = _check_step(b, n, s, 1.0, dt, chi=0.0)
+    assert rc0 == N.KC_OK and dmax0 == pytest.approx(0.25, rel=1e-12)
+
+
+def test_stability_check_with_per_step_noise_takes_the_largest_sigma():
+    b, n, s = _chemotactic_front()
+    # sigma0 (1 + a) = 3 scales every diffusivity and the chemotactic coefficient
+    rc, dmax = _check_step(b, n, None, 1.0, 0.05, chi=20.0, chi_law=N.KC_CHI_CONSTANT,
+                           noise=N.KC_NOISE_PER_STEP, sigma0=2.0, noise_amp=0.5)
+    want = _outflow_bound(b, n, 3.0 * s, 20.0, False)
+    assert dmax == pytest.approx(want, rel=1e-6)
+    assert rc == N.KC_OK and 0.05 <= want
+    assert _check_step(b, n, None, 1.0, 1.01 * want, chi=20.0, chi_law=N.KC_CHI_CONSTANT,
+                       noise=N.KC_NOISE_PER_STEP, sigma0=2.0, noise_amp=0.5)[0] == N.KC_EUNSTABLE
+    assert _check_step(b, n, None, 1.0, 0.05, chi=20.0)[0] == N.KC_EINVAL  # static sigma needed
+    bad = b.copy()
+    bad[3, 4] = np.nan
+    assert _check_step(bad, n, s, 1.0, 0.05)[0] == N.KC_ENONFINITE
+    assert _check_step(b, n, s, 1.0, -1.0)[0] == N.KC_EINVAL

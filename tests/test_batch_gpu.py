@@ -151,7 +151,15 @@ def test_error_paths_and_bounded_wait():
     with pytest.raises(N.KcError) as e:
         B.run(40, 10)
     assert e.value.code == N.KC_EHIP
+    # the stopped launch may have overwritten part of a level: the fields must be
+    # set again before the batch runs or returns them
     B.set_spin_limit(1 << 23)
+    with pytest.raises(N.KcError) as e:
+        B.run(40, 10)
+    assert e.value.code == N.KC_ESTATE
+    with pytest.raises(N.KcError) as e:
+        B.get_fields(0)
+    assert e.value.code == N.KC_ESTATE
     B.set_fields(0, b, n, s)
     B.run(40, 10)
     assert B.nsamples() == 4

@@ -266,17 +266,18 @@ def test_full_size_sampled_cells_match_oracle(cfg, launches):
 # ----------------------------------------------------------------------------
 # Long horizon: the 512^2 crop of the 16384^2 workload (n0 = 0.35, chi = 2),
 # 20000 steps, in the kernel configuration the shipped tuning database gives
-# the 16384^2 grid.  FP32 rounding (unit 6e-8) accumulating at most linearly
-# over 20000 steps bounds the normwise drift by about 1.2e-3; assert 2e-3.
+# the 16384^2 grid.  The FP32 error of the 128^2 workload after 2000 steps
+# (2.5e-5) grown linearly to 20000 steps is 2.5e-4 (measured here: 1.5e-4 for
+# b, 4e-5 for n); the bar is twice that, 5e-4.
 # ----------------------------------------------------------------------------
-def _shipped_tuning(key_part):
+def _shipped_tuning(key_part, exact=False):
     import json
     import os
     path = os.path.join(os.path.dirname(__file__), "..", "paper_1301_5058_amd", "tuning",
                         "gfx950.jsonl")
     for line in open(path):
         e = json.loads(line)
-        if key_part in e["key"]:
+        if (e["key"].endswith(key_part) if exact else key_part in e["key"]):
             return e["tsteps"], e["rows"], e["prefetch"]
     return None
 
@@ -300,9 +301,42 @@ def test_crop_512_long_run_matches_oracle():
     mass = abs(mass_g - od[0]) / od[0]
     print("512^2 x %d steps, tuning %s: normwise b %.3e n %.3e, mass %.3e, area radius %.6f vs %.6f"
           % (k["steps"], tuning, eb, en, mass, area_g, od[3]))
-    assert eb <= 2e-3 and en <= 2e-3
-    assert mass <= 2e-3
-    assert abs(area_g - od[3]) <= 0.01 * od[3]
+    assert eb <= 5e-4 and en <= 5e-4
+    assert mass <= 5e-4
+    assert abs(area_g - od[3]) <= 0.005 * od[3]
+
+
+def test_bench_configuration_whole_field_matches_oracle():
+    # the benchmark's own path: the 4096^2 FP32 workload (chi = 1) in the shipped
+    # tuning, kc_step_sample every 100 steps, 2000 steps; every cell of both
+    # fields against the FP64 oracle, and the last sample's mass and radii
+    from paper_1301_5058_amd.solver import Solver
+    cfg = workload.SINGLE_4096
+    nx, ny = cfg["nx"], cfg["ny"]
+    b, n, s = workload.fields(nx, ny, cfg["n0"], cfg["a"], cfg["seed"])
+    dt = workload.config_dt(b, n, s)
+    tuning = _shipped_tuning("|4096x4096|fp32|receptor", exact=True)
+    assert tuning is not None
+    S = Solver(nx, ny, dt=dt, chi=cfg["chi"], b_thr=0.5 * cfg["n0"])
+    S.set_fields(torch.from_numpy(b).cuda(), torch.from_numpy(n).cuda(), torch.from_numpy(s).cuda())
+    S.set_tuning(*tuning)
+    steps, every = 2000, 100
+    series = torch.zeros((steps // every, 5), dtype=torch.float64, device="cuda")
+    for i in range(steps // every):
+        S.step_sample(every, series[i])
+    gb, gn = S.get_fields()
+    last = series[-1].cpu().numpy()
+    S.close()
+    ob, on = oracle.run(b, n, s, 1.0, dt, steps, chi=cfg["chi"])
+    m, nu, r, ra = oracle.diag(ob, on, 1.0, 0.5 * cfg["n0"], area=True)
+    eb, en = normwise(gb, ob), normwise(gn, on)
+    print("4096^2 x %d steps, tuning %s: normwise b %.3e n %.3e; mass %.9g (oracle %.9g), "
+          "envelope radius %.6f (%.6f), area radius %.6f (%.6f)"
+          % (steps, tuning, eb, en, last[1], m, last[3], r, last[4], ra))
+    assert last[0] == pytest.approx(steps * dt, rel=1e-15)
+    assert eb <= 1e-4 and en <= 1e-4
+    assert abs(last[1] - m) <= 5e-3 * m and abs(last[2] - nu) <= 5e-3 * nu
+    assert abs(last[3] - r) <= 5e-3 * r and abs(last[4] - ra) <= 5e-3 * ra
 
 
 # ----------------------------------------------------------------------------

@@ -125,3 +125,61 @@ def test_threshold_speed_kernel_matches_oracle():
         n0, chi = pts[k]
         assert abs(got2[k] - oracle.cstar(n0, chi, 2.0)) <= 1e-5 * got2[k]
     assert np.all(np.isnan(bad))
+
+
+def test_gradient_elementwise_against_reference():
+    # every entry of every tensor against the FP64 network with the same
+    # bfloat16 rounding points; the differences left are float32 accumulation
+    # and bfloat16 roundings that fall on the other side of a tie
+    S, p = _model()
+    X, y = _data(1000, 9)
+    g, _ = S.grad(X, y)
+    _, gr = mlp_ref.loss_and_grad(p.astype(np.float64), X.astype(np.float64), y, **MAPS)
+    for name, off, shape in mlp_ref.LAYOUT:
+        size = int(np.prod(shape)) if shape else 1
+        a, b = g[off:off + size].astype(np.float64), gr[off:off + size]
+        err = np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-30)
+        print("%s max elementwise err / max|g| %.2e" % (name, err))
+        assert err <= 2e-2, name
+    S.close()
+
+
+def test_adam_steps_match_reference_adam():
+    # ks_train with one full-batch iteration applies Adam to the gradient that
+    # ks_grad returns at the same parameters (same kernel, same partials, same
+    # summation order).  The FP64 Adam of the oracle fed those gradients must
+    # reproduce the parameters after every step, element by element, to the
+    # float32 rounding of the parameters and the moments.
+    S, p = _model()
+    X, y = _data(300, 8)
+    lr = 1e-3
+    theta = p.astype(np.float64)
+    m = np.zeros_like(theta)
+    v = np.zeros_like(theta)
+    k = 6
+    for t in range(1, k + 1):
+        g, _ = S.grad(X, y)
+        S.train(X, y, iters=1, batch=len(X), lr=lr)
+        theta, m, v = mlp_ref.adam_step(theta, g.astype(np.float64), m, v, t, lr)
+        got = S.get_params().astype(np.float64)
+        err = np.abs(got - theta)
+        tol = t * (1.2e-7 * np.abs(theta) + 4e-6 * lr) + 1e-30
+        print("step %d: max |p - p_ref| %.3e, max err / tol %.3f, max |step| %.3e"
+              % (t, err.max(), np.max(err / tol), np.max(np.abs(got - p))))
+        assert np.all(err <= tol), t
+    # the same steps again with the oracle's own gradients: the trajectories
+    # differ only where a gradient entry is near zero and its float32 value
+    # has a different sign or size (Adam normalises every entry to about lr)
+    theta = p.astype(np.float64)
+    m = np.zeros_like(theta)
+    v = np.zeros_like(theta)
+    S.set_params(p)
+    S.train(X, y, iters=3, batch=len(X), lr=lr)
+    for t in range(1, 4):
+        _, gr = mlp_ref.loss_and_grad(theta, X.astype(np.float64), y, **MAPS)
+        theta, m, v = mlp_ref.adam_step(theta, gr, m, v, t, lr)
+    d = np.abs(S.get_params().astype(np.float64) - theta)
+    print("3 steps, oracle gradients: median |dp| %.2e, p99 %.2e, max %.2e (lr %.0e)"
+          % (np.median(d), np.quantile(d, 0.99), d.max(), lr))
+    assert np.quantile(d, 0.99) <= 0.1 * 3 * lr and d.max() <= 2 * 3 * lr
+    S.close()
