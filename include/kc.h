@@ -149,6 +149,23 @@ int kc_diagnostics_device(kc_ctx *ctx, double *dev_out5);
  * the reference kernel selected it runs kc_step and kc_diagnostics_device. */
 int kc_step_sample(kc_ctx *ctx, int64_t nsteps, double *dev_out5);
 
+/* kc_step_sample for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same launches and results as kc_step_sample (fields, time and radii
+ * bit for bit; mass and nutrient are the same sums in the same order), but the
+ * per-strip partials of the last launch go to a fixed scratch array that the
+ * library keeps in device memory (4 doubles per strip, at most
+ * KC_NOALLOC_MAX_STRIPS strips: 4 MiB per device, held until the process
+ * ends) instead of a buffer of the context, and the call allocates nothing.
+ * Every strip writes its own partials before the final pass reads them, so
+ * nothing has to be cleared between calls.  All calls on one device share
+ * that array: calls that overlap in time on one device (other streams or
+ * contexts) race and must be ordered by the caller.  KC_EINVAL when the last
+ * launch would have more strips than that (taller strips, kc_set_tuning, fix
+ * it) or when the reference kernel is selected; otherwise as kc_step_sample. */
+#define KC_NOALLOC_MAX_STRIPS 131072
+int kc_step_sample_noalloc(kc_ctx *ctx, int64_t nsteps, double *dev_out5);
+
 /* Copy the current level out (synchronous).  Either pointer may be NULL. */
 int kc_get_fields(kc_ctx *ctx, void *b, void *n, int mem);
 

@@ -9,6 +9,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <utility>
 #include <vector>
@@ -158,10 +159,25 @@ template <typename R> Fields<R> make_fields(const kc_ctx *c)
     return f;
 }
 
+// Depth (time steps) of the last fused launch of a kc_step of nsteps >= 1.
+int last_launch_depth(const kc_ctx *c, int64_t nsteps)
+{
+    int d = 1;
+    while (nsteps > 0) {
+        const int64_t want = nsteps < c->tune.tsteps ? nsteps : c->tune.tsteps;
+        d = kc::stream_depth_at_most((int)want, c->p.integrator);
+        nsteps -= d;
+    }
+    return d;
+}
+
 // nsteps steps; with dev_out5 non-null (fused kernel only) the last launch also
 // folds the level it stores into per-strip partials and a final pass writes the
-// diagnostics of that level to dev_out5.
-template <typename R> int step_impl(kc_ctx *c, int64_t nsteps, double *dev_out5 = nullptr)
+// diagnostics of that level to dev_out5.  The partials go to ext_parts when it
+// is non-null (the caller has checked that the last launch's strips fit),
+// otherwise to the context's own buffer, grown when needed.
+template <typename R>
+int step_impl(kc_ctx *c, int64_t nsteps, double *dev_out5 = nullptr, double *ext_parts = nullptr)
 {
     const Coef<R> k = make_coef<R>(c);
     const int integ = c->p.integrator;
@@ -211,7 +227,9 @@ template <typename R> int step_impl(kc_ctx *c, int64_t nsteps, double *dev_out5 
                 nstrips = kc::stream_geom(c->p.precision, kc::stream_levels(integ, t.tsteps),
                                           c->nx, c->ny, t.rows)
                               .nstrips;
-                if ((size_t)nstrips > c->sparts_cap) {
+                if (ext_parts) {
+                    d.parts = ext_parts;
+                } else if ((size_t)nstrips > c->sparts_cap) {
                     if (c->sparts) {
                         KC_HIP(c, hipStreamSynchronize(c->stream));
                         KC_HIP(c, hipFree(c->sparts));
@@ -221,7 +239,8 @@ template <typename R> int step_impl(kc_ctx *c, int64_t nsteps, double *dev_out5 
                     KC_HIP(c, hipMalloc((void **)&c->sparts, (size_t)nstrips * 4 * sizeof(double)));
                     c->sparts_cap = (size_t)nstrips;
                 }
-                d.parts = c->sparts;
+                if (!ext_parts)
+                    d.parts = c->sparts;
             }
             e = kc::launch_stream<R>(f, k, c->p.chi_law, integ, t, c->stream, zp,
                                      d.parts ? &d : nullptr);
@@ -316,7 +335,48 @@ int stability(double h, double dt, double D_n, double max_snb, double max_rate, 
 
 } // namespace kc
 
+// Scratch of kc_step_sample_noalloc: the per-strip diagnostics partials (4
+// doubles per strip) of its last step launch.  Each device holds its own copy
+// for the life of the process; host code reaches it only through the address
+// hipGetSymbolAddress returns for that device (scratch_parts below).
+static __device__ __align__(256) double scratch[4 * (size_t)KC_NOALLOC_MAX_STRIPS];
+
 namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on `device` (looked up once per device, with
+// that device current).
+hipError_t scratch_parts(int device, double **out)
+{
+    if (device < 0 || device >= kMaxDevices)
+        return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        int cur = 0;
+        hipError_t e = hipGetDevice(&cur);
+        if (e != hipSuccess)
+            return e;
+        if (cur != device && (e = hipSetDevice(device)) != hipSuccess)
+            return e;
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (cur != device) {
+            const hipError_t e2 = hipSetDevice(cur);
+            if (e == hipSuccess)
+                e = e2;
+        }
+        if (e != hipSuccess)
+            return e;
+        if (!p)
+            return hipErrorInvalidSymbol;
+        g_scratch_ptr[device] = (double *)p;
+    }
+    *out = g_scratch_ptr[device];
+    return hipSuccess;
+}
 
 bool sizes_ok(int nx, int ny)
 {
@@ -674,6 +734,33 @@ int kc_step_sample(kc_ctx *c, int64_t nsteps, double *dev_out5)
     }
     return c->p.precision == KC_FP32 ? step_impl<float>(c, nsteps, dev_out5)
                                      : step_impl<double>(c, nsteps, dev_out5);
+}
+
+int kc_step_sample_noalloc(kc_ctx *c, int64_t nsteps, double *dev_out5)
+{
+    if (!c || !dev_out5)
+        return KC_EINVAL;
+    c->err.clear();
+    if (nsteps < 1)
+        return fail(c, KC_EINVAL, "kc_step_sample_noalloc needs at least one step");
+    if (!c->has_fields)
+        return fail(c, KC_ESTATE, "kc_step_sample_noalloc before kc_set_fields");
+    if (c->ref)
+        return fail(c, KC_EINVAL,
+                    "kc_step_sample_noalloc runs the fused kernel only (reference kernel selected)");
+    const int d = last_launch_depth(c, nsteps);
+    const int nstrips = kc::stream_geom(c->p.precision, kc::stream_levels(c->p.integrator, d),
+                                        c->nx, c->ny, c->tune.rows)
+                            .nstrips;
+    if (nstrips > KC_NOALLOC_MAX_STRIPS)
+        return fail(c, KC_EINVAL,
+                    "the last launch has %d strips, more than the %d the scratch of "
+                    "kc_step_sample_noalloc holds (use taller strips or kc_step_sample)",
+                    nstrips, KC_NOALLOC_MAX_STRIPS);
+    double *parts = nullptr;
+    KC_HIP(c, scratch_parts(c->device, &parts));
+    return c->p.precision == KC_FP32 ? step_impl<float>(c, nsteps, dev_out5, parts)
+                                     : step_impl<double>(c, nsteps, dev_out5, parts);
 }
 
 int kc_diagnostics_device(kc_ctx *c, double *dev_out5)

@@ -56,6 +56,7 @@ _SIGS = {
     "kc_diagnostics": (c_int32, [c_void_p, P_double, P_double, P_double]),
     "kc_diagnostics_device": (c_int32, [c_void_p, c_void_p]),
     "kc_step_sample": (c_int32, [c_void_p, c_int64, c_void_p]),
+    "kc_step_sample_noalloc": (c_int32, [c_void_p, c_int64, c_void_p]),
     "kc_get_fields": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32]),
     "kc_time": (c_int32, [c_void_p, P_double, ctypes.POINTER(c_int64)]),
     "kc_suggest_dt": (c_double, [c_double, c_double, c_double]),

@@ -108,6 +108,16 @@ class Solver:
         N.check(N.lib().kc_step_sample(self.ctx, int(nsteps), ctypes.c_void_p(out5.data_ptr())),
                 self.ctx)
 
+    def step_sample_noalloc(self, nsteps, out5):
+        """step_sample through kc_step_sample_noalloc: the same results, with
+        the diagnostics partials in the library's fixed device scratch (no
+        device allocation in the call)."""
+        if out5.dtype != torch.float64 or not out5.is_cuda or out5.numel() < 5 or \
+                not out5.is_contiguous():
+            raise ValueError("out5 must be a contiguous float64 CUDA tensor with >= 5 elements")
+        N.check(N.lib().kc_step_sample_noalloc(self.ctx, int(nsteps),
+                                               ctypes.c_void_p(out5.data_ptr())), self.ctx)
+
     def diagnostics(self):
         m, nu, r = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
         N.check(N.lib().kc_diagnostics(self.ctx, ctypes.byref(m), ctypes.byref(nu),

@@ -44,6 +44,7 @@ def test_strerror_and_null_context():
     L.kc_destroy(None)
     assert L.kc_step(None, 1) == N.KC_EINVAL
     assert L.kc_step_sample(None, 1, None) == N.KC_EINVAL
+    assert L.kc_step_sample_noalloc(None, 1, None) == N.KC_EINVAL
     assert L.kc_set_fields(None, None, None, None, 0) == N.KC_EINVAL
     assert L.kc_diagnostics(None, None, None, None) == N.KC_EINVAL
     assert L.kc_get_fields(None, None, None, 0) == N.KC_EINVAL
