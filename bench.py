@@ -82,7 +82,12 @@ def kernel_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(tsteps, rows, prefetch):
+def _tuning_matches(kv, tsteps, rows, prefetch, waves):
+    return (int(kv.get("tsteps", -1)), int(kv.get("rows", -1)), int(kv.get("prefetch", -1)),
+            int(kv.get("waves", 1))) == (tsteps, rows, prefetch, waves)
+
+
+def measured_traffic(tsteps, rows, prefetch, waves=1):
     """HBM bytes per step-kernel launch from the committed PMC summary, or None
     when the summary is missing, was taken for another configuration, or for
     older kernel sources."""
@@ -93,8 +98,7 @@ def measured_traffic(tsteps, rows, prefetch):
     kv = dict(re.findall(r"^(\w+)\s*=\s*(\S+)", txt, flags=re.M))
     if kv.get("kernel_sources_sha256_16") != kernel_hash():
         return None
-    if (int(kv.get("tsteps", -1)), int(kv.get("rows", -1)), int(kv.get("prefetch", -1))) != \
-            (tsteps, rows, prefetch):
+    if not _tuning_matches(kv, tsteps, rows, prefetch, waves):
         return None
     try:
         return float(kv["hbm_bytes_per_launch"])
@@ -102,7 +106,7 @@ def measured_traffic(tsteps, rows, prefetch):
         return None
 
 
-def measured_counters(tsteps, rows, prefetch):
+def measured_counters(tsteps, rows, prefetch, waves=1):
     """VALU counters of the step kernel from the committed PMC summary (issued
     VALU instructions per useful cell-update, VALU busy fraction), or None when
     the summary is missing or was taken for another configuration or older
@@ -114,8 +118,7 @@ def measured_counters(tsteps, rows, prefetch):
     kv = dict(re.findall(r"^(\w+)\s*=\s*(\S+)", txt, flags=re.M))
     if kv.get("kernel_sources_sha256_16") != kernel_hash():
         return None
-    if (int(kv.get("tsteps", -1)), int(kv.get("rows", -1)), int(kv.get("prefetch", -1))) != \
-            (tsteps, rows, prefetch):
+    if not _tuning_matches(kv, tsteps, rows, prefetch, waves):
         return None
     try:
         return {"valu_issued_per_update": float(kv["valu_issued_per_update"]),
@@ -251,8 +254,9 @@ def run(args):
     S.set_fields(tb, tn, ts)
     tuned = S.autotune(effort=0 if args.quick_tune else 1, use_cache=True)
     tsteps, rows, pf = S.tuning()
-    progress("autotuned 4096^2 fp32: T=%d rows=%d prefetch=%d (%.1f GCell/s)"
-             % (tsteps, rows, pf, tuned))
+    waves = S.strip_waves()
+    progress("autotuned 4096^2 fp32: T=%d rows=%d prefetch=%d waves/strip=%d (%.1f GCell/s)"
+             % (tsteps, rows, pf, waves, tuned))
 
     time_steps = args.steps * SAMPLE_EVERY
     series = torch.zeros((args.steps + 1, 5), dtype=torch.float64, device=dev)
@@ -270,8 +274,9 @@ def run(args):
     progress("timed %d steps (%d time steps): %.1f GCell/s" % (args.steps, time_steps, value))
     launch_ms = launch_probe(S, stream)
     main_rl, other_rl = roofline("fp32", cells, tsteps, launch_ms)
-    main_rl["traffic"] = measured_traffic(tsteps, rows, pf)
-    main_rl["kernel"] = "step_stream<float,T=%d,PF=%d>" % (tsteps, pf)
+    main_rl["traffic"] = measured_traffic(tsteps, rows, pf, waves)
+    main_rl["kernel"] = "%s<float,T=%d,PF=%d>" % ("step_split" if waves == 2 else "step_stream",
+                                                 tsteps, pf)
     main_rl["launch_us"] = round(launch_ms * 1e3, 3)
     main_rl["other_bound"] = other_rl
     # the same launch priced in flops: 55 per update against the published
@@ -281,7 +286,7 @@ def run(args):
                             "achieved_tflops": round(tflops, 2),
                             "frac_of_157_3": round(tflops / FP32_PEAK_TFLOPS, 4),
                             "frac_of_nonpacked_78_6": round(tflops / FP32_NONPACKED_TFLOPS, 4)}
-    main_rl["counters"] = measured_counters(tsteps, rows, pf)
+    main_rl["counters"] = measured_counters(tsteps, rows, pf, waves)
     S.close()
 
     out = {
@@ -302,7 +307,7 @@ def run(args):
                                "chi=1 receptor law, forward Euler; one step = 100 time steps "
                                "+ fused diagnostics",
                    "nx": nx, "ny": ny, "dt": dt, "chi": chi, "tsteps": tsteps, "rows": rows,
-                   "prefetch": pf, "autotune_gcell_s": round(tuned, 1)},
+                   "prefetch": pf, "waves_per_strip": waves, "autotune_gcell_s": round(tuned, 1)},
         "roofline": main_rl,
         "effective_hbm_frac": round(value * 1e9 * 20 / (HBM_PEAK_GBS * 1e9), 4),
         "wall_s": round(wall, 3),
@@ -340,6 +345,7 @@ def single_variant(nx, n0, a, chi, precision, steps, tune_effort=0, integrator="
         S.set_fields(*(torch.from_numpy(x).cuda() for x in (b, n)))
     S.autotune(effort=tune_effort, use_cache=True)
     T, rows, pf = S.tuning()
+    waves = S.strip_waves()
     S.step(100)
     ms = timed_run(S, stream, steps)
     lm = launch_probe(S, stream, 20)
@@ -352,7 +358,7 @@ def single_variant(nx, n0, a, chi, precision, steps, tune_effort=0, integrator="
     S.close()
     return {"gcell_s": round(nx * nx * steps / (ms / 1e3) / 1e9, 2), "steps": steps,
             "integrator": integrator, "noise": noise is not None, "tsteps": T, "rows": rows,
-            "prefetch": pf,
+            "prefetch": pf, "waves_per_strip": waves,
             "launch_us": round(lm * 1e3, 2), "roofline_bound": rl["bound"],
             "roofline_frac": rl["frac"], "other_bound": other["bound"],
             "other_frac": other["frac"]}
@@ -374,12 +380,14 @@ def hires(steps):
     del b, n, s
     S.autotune(effort=0, use_cache=True)
     T, rows, pf = S.tuning()
+    waves = S.strip_waves()
     series = torch.zeros((steps // SAMPLE_EVERY + 2, 5), dtype=torch.float64, device="cuda")
     ms = timed_run(S, stream, steps, series)
     d = series[steps // SAMPLE_EVERY - 1].cpu().numpy()
     S.close()
     res = {"nx": c["nx"], "steps": steps, "gcell_s": round(c["nx"] * c["ny"] * steps / (ms / 1e3) / 1e9, 2),
-           "tsteps": T, "rows": rows, "prefetch": pf, "seconds": round(ms / 1e3, 3),
+           "tsteps": T, "rows": rows, "prefetch": pf, "waves_per_strip": waves,
+           "seconds": round(ms / 1e3, 3),
            "final_envelope_radius": float(d[3]), "final_area_radius": float(d[4])}
     return res
 
@@ -496,11 +504,19 @@ def front1d_speeds():
     c* of the scalar front equation."""
     from paper_1301_5058_amd import front1d
     r = front1d.run_front1d()
+    v1, v2 = r["velocity_halves"]
+    # "steady": the speeds over the two halves of the window agree within 10 %
+    # (a travelling front); otherwise the window speed is the mean of a
+    # transient (strong chemotaxis bursts ahead and decelerates, poor nutrient
+    # stalls).  "above_cbar": faster than c-bar by more than the 1.5 % that the
+    # oracle's 400 -> 3200-cell resolution study moves any speed.
     rows = [{"n0": p[0], "chi0": p[1], "v": round(float(v), 5), "steady": bool(st),
+             "v_halves": [round(float(a), 5), round(float(b), 5)],
+             "above_cbar": bool(v > 1.015 * cb),
              "cbar": round(float(cb), 5), "cstar": round(float(cs), 5),
              "v_over_cbar": round(float(v / cb), 4), "v_over_cstar": round(float(v / cs), 4)}
-            for p, v, st, cb, cs in zip(r["points"], r["velocity"], r["steady"], r["cbar"],
-                                        r["cstar"])]
+            for p, v, st, a, b, cb, cs in zip(r["points"], r["velocity"], r["steady"], v1, v2,
+                                              r["cbar"], r["cstar"])]
     return {"cells": r["cells"], "steps": r["steps"], "window": list(r["window"]),
             "gpu_s": round(r["gpu_s"], 3), "wall_s": round(r["wall_s"], 3), "fronts": rows}
 

@@ -209,17 +209,32 @@ int kc_check_step(int32_t nx, int32_t ny, int precision, const void *b0, const v
 int kc_set_tuning(kc_ctx *ctx, int32_t tsteps, int32_t rows, int32_t prefetch);
 int kc_get_tuning(const kc_ctx *ctx, int32_t *tsteps, int32_t *rows, int32_t *prefetch);
 
-/* Pick the fused-kernel configuration (as kc_set_tuning) by timing candidate
- * launches on the context's own fields: each launch reads the current level
- * and writes the scratch level, so the state is unchanged.  effort 0 tries 16
- * candidates, 1 the full grid of 120; both add, per depth and prefetch, the
- * rows per strip that fill 1..8 whole rounds of the wavefronts the device
- * holds at once.  With use_cache != 0 a matching entry
- * of the file named by the environment variable KC_AUTOTUNE_CACHE (one JSON
- * object per line, keyed by device, grid, precision and law) is used instead
- * of timing, and a new result is appended to it.  *gcell_s (may be NULL)
- * receives the best measured rate in 1e9 cell-updates/s (0 when the cache
- * answered).  Requires fields (KC_ESTATE).  Synchronous. */
+/* Wavefronts per strip of the fused kernel: 1 (one wavefront advances a strip
+ * through all the levels of a launch) or 2 (two wavefronts of one workgroup
+ * share the strip, the first running the first half of the levels and
+ * handing each row to the second through LDS: each holds half the state, so
+ * twice as many wavefronts fit on a SIMD for the same strips).  2 applies to
+ * launches whose levels split into halves of whole time steps (an even number
+ * of Euler steps, two Runge-Kutta steps); other launches use 1.  Results do
+ * not depend on it.  KC_EINVAL for other values. */
+int kc_set_strip_waves(kc_ctx *ctx, int32_t waves);
+int kc_get_strip_waves(const kc_ctx *ctx, int32_t *waves);
+
+/* Pick the fused-kernel configuration (as kc_set_tuning and
+ * kc_set_strip_waves) by timing candidate launches on the context's own
+ * fields: each launch reads the current level and writes the scratch level,
+ * so the state is unchanged.  effort 0 tries 4 depths x 4 strip heights with
+ * prefetch 4, effort 1 6 depths x 10 heights x prefetch 2 and 4; each with one
+ * wavefront per strip and, where the depth splits, two; both add, per depth,
+ * prefetch and wavefront count, the strip heights that fill 1..8 whole rounds
+ * of the strips the device holds at once.  With use_cache != 0 a matching
+ * entry of the file named by the environment variable KC_AUTOTUNE_CACHE (one
+ * JSON object per line, keyed by device, grid, precision, law, integrator and
+ * noise mode) is used instead of timing, and a new result is appended to it.
+ * *gcell_s (may be NULL) receives the best measured rate in 1e9
+ * cell-updates/s, or when the cache answered the rate stored with its entry
+ * (0 if it has none).  Requires fields (KC_ESTATE).
+ * Synchronous. */
 int kc_autotune(kc_ctx *ctx, int32_t effort, int32_t use_cache, double *gcell_s);
 
 /* Use the one-step-per-launch global-memory kernel (1) or the fused,

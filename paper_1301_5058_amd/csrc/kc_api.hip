@@ -34,7 +34,7 @@ struct kc_ctx {
     int cur = 0;
     bool has_fields = false;
     int64_t steps = 0;
-    kc::Tuning tune{2, 32, 4};
+    kc::Tuning tune{2, 32, 4, 1};
     bool ref = false;
     double *dparts = nullptr; // diagnostics partials, then out5 (5 doubles)
     double *dout5 = nullptr;
@@ -103,7 +103,8 @@ int default_rows(int precision, int chi_law, int integrator, bool noise, const k
                  int nx, int ny)
 {
     // no half-empty last round; long strips amortise the warm-up rows at either end
-    const int w = kc::resident_waves(precision, chi_law, integrator, t.tsteps, t.prefetch, noise);
+    const int w =
+        kc::resident_waves(precision, chi_law, integrator, t.tsteps, t.prefetch, noise, t.waves);
     const int levels = kc::stream_levels(integrator, t.tsteps);
     for (int q = 1; q <= 64 && w > 0; ++q) {
         const int r = kc::round_fitted_rows(precision, levels, nx, ny, w, q);
@@ -388,13 +389,13 @@ template <typename R> int autotune_impl(kc_ctx *c, int effort, double *best_out)
 {
     const Coef<R> k = make_coef<R>(c);
     const Fields<R> f = make_fields<R>(c); // current level in, scratch level out
-    kc::Tuning cand[256];
+    kc::Tuning cand[512];
     int n = 0;
     const bool noise = c->p.noise == KC_NOISE_PER_STEP;
     const kc::Noise<R> z = make_noise<R>(c);
     const kc::Noise<R> *zp = noise ? &z : nullptr;
     kc::tuning_candidates(effort, c->p.precision, c->p.chi_law, c->p.integrator, noise, c->nx,
-                          c->ny, cand, &n, 256);
+                          c->ny, cand, &n, 512);
     const double cells = (double)c->nx * c->ny;
     // pass 1: every candidate once; pass 2: the six fastest again, twice each
     // with longer runs, keeping each one's best (single timings are noisy)
@@ -864,6 +865,25 @@ int kc_get_tuning(const kc_ctx *c, int32_t *tsteps, int32_t *rows, int32_t *pref
     return KC_OK;
 }
 
+int kc_set_strip_waves(kc_ctx *c, int32_t waves)
+{
+    if (!c)
+        return KC_EINVAL;
+    c->err.clear();
+    if (waves != 1 && waves != 2)
+        return fail(c, KC_EINVAL, "wavefronts per strip must be 1 or 2 (got %d)", waves);
+    c->tune.waves = waves;
+    return KC_OK;
+}
+
+int kc_get_strip_waves(const kc_ctx *c, int32_t *waves)
+{
+    if (!c || !waves)
+        return KC_EINVAL;
+    *waves = c->tune.waves;
+    return KC_OK;
+}
+
 int kc_autotune(kc_ctx *c, int32_t effort, int32_t use_cache, double *gcell_s)
 {
     if (!c)
@@ -879,8 +899,11 @@ int kc_autotune(kc_ctx *c, int32_t effort, int32_t use_cache, double *gcell_s)
     if (gcell_s)
         *gcell_s = 0.0;
     kc::Tuning t;
-    if (use_cache && kc::cache_lookup(key, c->p.integrator, &t)) {
+    double stored = 0.0;
+    if (use_cache && kc::cache_lookup(key, c->p.integrator, &t, &stored)) {
         c->tune = t;
+        if (gcell_s)
+            *gcell_s = stored;
         return KC_OK;
     }
     double g = 0.0;

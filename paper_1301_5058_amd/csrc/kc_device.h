@@ -37,8 +37,15 @@ template <typename R> struct Coef {
 template <typename R> __device__ __forceinline__ R rcp(R x);
 // v_rcp_f32: 1 ulp reciprocal; (1+n)^2 >= 1 so no denormal or overflow case.
 template <> __device__ __forceinline__ float rcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
-// correctly rounded double division
-template <> __device__ __forceinline__ double rcp<double>(double x) { return 1.0 / x; }
+// v_rcp_f64 refined by two Newton-Raphson steps r <- r + r (1 - x r), each an
+// FMA pair: within an ulp of 1/x for the arguments here ((1+n)^2 in [1, 16]),
+// five instructions instead of the correctly rounded division's ten.
+template <> __device__ __forceinline__ double rcp<double>(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    r = __builtin_fma(r, __builtin_fma(-x, r, 1.0), r);
+    return __builtin_fma(r, __builtin_fma(-x, r, 1.0), r);
+}
 
 __device__ __forceinline__ float fmaR(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fmaR(double a, double b, double c) { return __builtin_fma(a, b, c); }

@@ -34,9 +34,10 @@ template <typename R> struct Fields {
 };
 
 struct Tuning {
-    int tsteps;   // time steps fused in one launch (Euler, or Runge-Kutta: 2 levels each)
-    int rows;     // output rows per wavefront strip
-    int prefetch; // rows loaded ahead (2 or 4)
+    int tsteps;    // time steps fused in one launch (Euler, or Runge-Kutta: 2 levels each)
+    int rows;      // output rows per wavefront strip
+    int prefetch;  // rows loaded ahead (2 or 4)
+    int waves = 1; // wavefronts per strip: 1 (all levels) or 2 (levels split in halves)
 };
 
 // Integrators (kc.h's KC_EULER / KC_RK2).
@@ -47,11 +48,17 @@ int stream_depth_at_most(int t, int integrator);
 // Levels (Euler stages) of a launch of `tsteps` steps: the halo width.
 int stream_levels(int integrator, int tsteps);
 
-// Launch geometry of the fused kernel (for the planner and the autotuner).
+// Launch geometry of the fused kernel (for the planner and the autotuner): a
+// whole-strip launch packs four strips into a workgroup, a split launch (two
+// wavefronts per strip) one strip.
 struct StreamGeom {
     int nsx, nsy, nstrips, nblocks_padded, out_cols;
 };
-StreamGeom stream_geom(int precision, int levels, int nx, int ny, int rows);
+StreamGeom stream_geom(int precision, int levels, int nx, int ny, int rows, int waves = 1);
+// Wavefronts per strip a launch of `levels` levels actually uses when `waves`
+// are asked for: 2 only where the levels split into two halves of whole time
+// steps (an even count; with Runge-Kutta an even number of steps per half).
+int launch_waves(int integrator, int levels, int waves);
 
 // Diagnostics fused into a fused-kernel launch: strip k folds the cells it
 // stores into parts[4k .. 4k + 3] = {sum b, sum n, max squared distance from
@@ -90,21 +97,23 @@ hipError_t time_stream(const Fields<R> &f, const Coef<R> &c, int chi_law, int in
 // that the device holds at once: blocks per compute unit x 4 x compute units
 // (0 on error).
 int resident_waves(int precision, int chi_law, int integrator, int tsteps, int prefetch,
-                   bool noise = false);
+                   bool noise = false, int waves = 1);
 // Rows per strip such that the strips of a launch of `levels` levels fill at
-// most `rounds` rounds of `waves` resident wavefronts (0 when none does).
-int round_fitted_rows(int precision, int levels, int nx, int ny, int waves, int rounds);
+// most `rounds` rounds of `strips` resident strips (0 when none does).
+int round_fitted_rows(int precision, int levels, int nx, int ny, int strips, int rounds);
 
 // Candidate configurations of the autotuner: effort 0 is a short list, 1 the
 // full grid (tsteps in {1,2,3,4,6,8}, at most 3 for Runge-Kutta, rows in
-// 8..256, prefetch 2 or 4); both add, per depth, the rows that fill 1..8 whole
-// rounds of resident wavefronts.
+// 8..256, prefetch 2 or 4), each with one wavefront per strip and, where the
+// depth splits into halves of whole steps, two; both add, per depth and
+// wavefront count, the rows that fill 1..8 whole rounds of resident strips.
 void tuning_candidates(int effort, int precision, int chi_law, int integrator, bool noise,
                        int nx, int ny, Tuning *out, int *n, int cap);
 
 // Autotune cache: one JSON object per line, keyed by device, grid, precision,
 // sensitivity law and (for Runge-Kutta) integrator.  Path from KC_AUTOTUNE_CACHE, else none.
-bool cache_lookup(const char *key, int integrator, Tuning *t);
+// The last entry for `key`; *gcells (if non-null) gets its stored rate (0 if none).
+bool cache_lookup(const char *key, int integrator, Tuning *t, double *gcells = nullptr);
 void cache_store(const char *key, const Tuning &t, double gcells);
 int device_key(char *buf, size_t n, int nx, int ny, int precision, int chi_law, int integrator,
                bool noise = false);

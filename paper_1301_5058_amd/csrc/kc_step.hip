@@ -85,7 +85,7 @@ int stream_depth_at_most(int t, int integrator)
 
 int stream_levels(int integrator, int tsteps) { return integrator == 0 ? tsteps : 2 * tsteps; }
 
-StreamGeom stream_geom(int precision, int levels, int nx, int ny, int rows)
+StreamGeom stream_geom(int precision, int levels, int nx, int ny, int rows, int waves)
 {
     const int vec = precision == 0 ? 4 : 2;
     const int hx = (levels + vec - 1) / vec * vec;
@@ -94,9 +94,18 @@ StreamGeom stream_geom(int precision, int levels, int nx, int ny, int rows)
     g.nsx = (nx + g.out_cols - 1) / g.out_cols;
     g.nsy = (ny + rows - 1) / rows;
     g.nstrips = g.nsx * g.nsy;
-    const int nblocks = (g.nstrips + 3) / 4;
+    const int nblocks = waves == 2 ? g.nstrips : (g.nstrips + 3) / 4;
     g.nblocks_padded = (nblocks + 7) / 8 * 8;
     return g;
+}
+
+int launch_waves(int integrator, int levels, int waves)
+{
+    if (waves != 2 || levels % 2 != 0)
+        return 1;
+    if (integrator != 0 && (levels / 2) % 2 != 0)
+        return 1;
+    return 2;
 }
 
 template <typename R>
@@ -122,16 +131,17 @@ static StepArgs<R> make_args(const Fields<R> &f, const Coef<R> &c)
 }
 
 template <typename R>
-static const void *stream_kernel(int chi_law, int integrator, bool noise, int levels, int pf)
+static const void *stream_kernel(int chi_law, int integrator, bool noise, int levels, int pf,
+                                 int waves)
 {
     if ((pf != 2 && pf != 4) || (integrator != 0 && integrator != 1) ||
         (chi_law != 0 && chi_law != 1))
         return nullptr;
     if (noise)
-        return integrator == 0 ? stream_kernel_for<R, false, true>(chi_law, levels, pf)
-                               : stream_kernel_for<R, true, true>(chi_law, levels, pf);
-    return integrator == 0 ? stream_kernel_for<R, false, false>(chi_law, levels, pf)
-                           : stream_kernel_for<R, true, false>(chi_law, levels, pf);
+        return integrator == 0 ? stream_kernel_for<R, false, true>(chi_law, levels, pf, waves)
+                               : stream_kernel_for<R, true, true>(chi_law, levels, pf, waves);
+    return integrator == 0 ? stream_kernel_for<R, false, false>(chi_law, levels, pf, waves)
+                           : stream_kernel_for<R, true, false>(chi_law, levels, pf, waves);
 }
 
 template <typename R>
@@ -139,13 +149,14 @@ hipError_t launch_stream(const Fields<R> &f, const Coef<R> &c, int chi_law, int 
                          const Tuning &t, hipStream_t s, const Noise<R> *z, const DiagReq *d)
 {
     const int levels = stream_levels(integrator, t.tsteps);
-    const void *fn = stream_kernel<R>(chi_law, integrator, z != nullptr, levels, t.prefetch);
+    const int waves = launch_waves(integrator, levels, t.waves);
+    const void *fn = stream_kernel<R>(chi_law, integrator, z != nullptr, levels, t.prefetch, waves);
     if (!fn || t.rows < 1)
         return hipErrorInvalidValue;
     StepArgs<R> a = make_args(f, c);
     if (z)
         a.z = *z;
-    const StreamGeom g = stream_geom(sizeof(R) == 4 ? 0 : 1, levels, f.nx, f.ny, t.rows);
+    const StreamGeom g = stream_geom(sizeof(R) == 4 ? 0 : 1, levels, f.nx, f.ny, t.rows, waves);
     a.rows = t.rows;
     a.nsx = g.nsx;
     a.nstrips = g.nstrips;
@@ -157,7 +168,7 @@ hipError_t launch_stream(const Fields<R> &f, const Coef<R> &c, int chi_law, int 
         a.cy = d->cy;
     }
     void *args[] = {&a};
-    return hipLaunchKernel(fn, dim3(g.nblocks_padded), dim3(256), args, 0, s);
+    return hipLaunchKernel(fn, dim3(g.nblocks_padded), dim3(waves == 2 ? 128 : 256), args, 0, s);
 }
 
 template <typename R, bool AVG, bool NOISE>
@@ -227,28 +238,31 @@ hipError_t time_stream(const Fields<R> &f, const Coef<R> &c, int chi_law, int in
 }
 
 int resident_waves(int precision, int chi_law, int integrator, int tsteps, int prefetch,
-                   bool noise)
+                   bool noise, int waves)
 {
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         return 0;
     const int levels = stream_levels(integrator, tsteps);
-    const void *fn = precision == 0
-                         ? stream_kernel<float>(chi_law, integrator, noise, levels, prefetch)
-                         : stream_kernel<double>(chi_law, integrator, noise, levels, prefetch);
+    waves = launch_waves(integrator, levels, waves);
+    const void *fn =
+        precision == 0 ? stream_kernel<float>(chi_law, integrator, noise, levels, prefetch, waves)
+                       : stream_kernel<double>(chi_law, integrator, noise, levels, prefetch, waves);
     int nb = 0;
-    if (!fn || hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, 256, 0) != hipSuccess)
+    if (!fn || hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, waves == 2 ? 128 : 256, 0) !=
+                   hipSuccess)
         return 0;
-    return nb * 4 * cus;
+    // resident strips: four per whole-strip workgroup, one per split workgroup
+    return nb * (waves == 2 ? 1 : 4) * cus;
 }
 
-int round_fitted_rows(int precision, int levels, int nx, int ny, int waves, int rounds)
+int round_fitted_rows(int precision, int levels, int nx, int ny, int strips, int rounds)
 {
-    if (waves <= 0 || rounds <= 0 || nx <= 0 || ny <= 0)
+    if (strips <= 0 || rounds <= 0 || nx <= 0 || ny <= 0)
         return 0;
     const StreamGeom g = stream_geom(precision, levels, nx, ny, 1);
-    const long m = (long)waves * rounds / g.nsx; // strip rows that fill `rounds` rounds
+    const long m = (long)strips * rounds / g.nsx; // strip rows that fill `rounds` rounds
     if (m <= 0)
         return 0;
     return (int)((ny + m - 1) / m);
@@ -266,33 +280,39 @@ void tuning_candidates(int effort, int precision, int chi_law, int integrator, b
     const int nt = effort ? 6 : 4, nr = effort ? 10 : 4;
     const int max_t = integrator == 0 ? 8 : 3;
     int k = 0;
-    auto add = [&](int t, int r, int p) {
+    auto add = [&](int t, int r, int p, int w) {
         for (int i = 0; i < k && i < cap; ++i)
-            if (out[i].tsteps == t && out[i].rows == r && out[i].prefetch == p)
+            if (out[i].tsteps == t && out[i].rows == r && out[i].prefetch == p &&
+                out[i].waves == w)
                 return;
         if (k < cap) {
             out[k].tsteps = t;
             out[k].rows = r;
             out[k].prefetch = p;
+            out[k].waves = w;
         }
         ++k;
     };
     for (int i = 0; i < nt; ++i) {
         if (ts[i] > max_t)
             continue;
-        for (int p = 0; p < (effort ? 2 : 1); ++p) {
-            const int pf = p ? 2 : 4;
-            for (int j = 0; j < nr; ++j)
-                add(ts[i], rs[j], pf);
-            // rows that fill a whole number of rounds of resident wavefronts
-            if (nx <= 0 || ny <= 0)
-                continue;
-            const int w = resident_waves(precision, chi_law, integrator, ts[i], pf, noise);
-            for (int q = 1; q <= 8; ++q) {
-                const int r = round_fitted_rows(precision, stream_levels(integrator, ts[i]), nx,
-                                                ny, w, q);
-                if (r >= 4 && r <= 512)
-                    add(ts[i], r, pf);
+        const int levels = stream_levels(integrator, ts[i]);
+        for (int w = 1; w <= 2; ++w) {
+            if (launch_waves(integrator, levels, w) != w)
+                continue; // no split kernel at this depth
+            for (int p = 0; p < (effort ? 2 : 1); ++p) {
+                const int pf = p ? 2 : 4;
+                for (int j = 0; j < nr; ++j)
+                    add(ts[i], rs[j], pf, w);
+                // rows that fill a whole number of rounds of resident strips
+                if (nx <= 0 || ny <= 0)
+                    continue;
+                const int st = resident_waves(precision, chi_law, integrator, ts[i], pf, noise, w);
+                for (int q = 1; q <= 8; ++q) {
+                    const int r = round_fitted_rows(precision, levels, nx, ny, st, q);
+                    if (r >= 4 && r <= 512)
+                        add(ts[i], r, pf, w);
+                }
             }
         }
     }

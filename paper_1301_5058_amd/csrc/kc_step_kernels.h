@@ -76,11 +76,133 @@ __global__ __launch_bounds__(256) void step_stream(StepArgs<R> a)
     }
 }
 
+// Split fused kernel: one strip per workgroup of two wavefronts, the first
+// running levels [0, T/2) from memory, the second levels [T/2, T) from the LDS
+// ring the first fills (stream_strip roles SPLIT_FIRST / SPLIT_SECOND).  Each
+// wavefront holds half the level state, so twice as many fit on a SIMD for
+// the same strips and halo; fields are the same bits as step_stream's.
+// Register budget of a split kernel: the FP32 four-level kernels with the
+// static agar field fit three wavefronts per SIMD (at most 168 VGPRs) without
+// spilling; the others keep the compiler's choice.
+template <typename R, int T, bool NOISE> struct SplitWaves {
+    static constexpr bool three = sizeof(R) == 4 && T == 4 && !NOISE;
+    static constexpr int lo = three ? 3 : 1;
+    static constexpr int hi = three ? 3 : 8;
+};
+
+template <typename R, int T, int LAW, int PF, bool RK, bool NOISE>
+__global__ __launch_bounds__(128)
+__attribute__((amdgpu_waves_per_eu(SplitWaves<R, T, NOISE>::lo, SplitWaves<R, T, NOISE>::hi)))
+void step_split(StepArgs<R> a)
+{
+    __shared__ SplitRing<R, PF> ring;
+    const int strip = __builtin_amdgcn_readfirstlane(xcd_block(a.nblocks_padded));
+    if (strip >= a.nstrips)
+        return; // both wavefronts of the workgroup leave together
+    const bool second = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)) != 0;
+    StripArgs<R> sa;
+    sa.b_in = a.b_in;
+    sa.n_in = a.n_in;
+    sa.sg = a.sg;
+    sa.b_out = a.b_out;
+    sa.n_out = a.n_out;
+    sa.nx = a.nx;
+    sa.ny = a.ny;
+    sa.pitch = a.pitch;
+    sa.rows = a.rows;
+    sa.c = a.c;
+    sa.z = a.z;
+    sa.b_thr = a.b_thr;
+    sa.cx = a.cx;
+    sa.cy = a.cy;
+    const int sx = strip % a.nsx, sy = strip / a.nsx;
+    constexpr int VEC = StreamShape<R>::VEC;
+    if (strip_inside<R, T>(sa, sx)) {
+        if (second)
+            stream_strip<R, T, LAW, PF, false, RK, NOISE, false, SPLIT_SECOND>(sa, sx, sy, &ring);
+        else
+            stream_strip<R, T, LAW, PF, false, RK, NOISE, false, SPLIT_FIRST>(sa, sx, sy, &ring);
+    } else if (!NOISE || a.nx % VEC == 0) {
+        if (second)
+            stream_strip<R, T, LAW, PF, true, RK, NOISE, false, SPLIT_SECOND>(sa, sx, sy, &ring);
+        else
+            stream_strip<R, T, LAW, PF, true, RK, NOISE, false, SPLIT_FIRST>(sa, sx, sy, &ring);
+    } else {
+        if (second)
+            stream_strip<R, T, LAW, PF, true, RK, NOISE, true, SPLIT_SECOND>(sa, sx, sy, &ring);
+        else
+            stream_strip<R, T, LAW, PF, true, RK, NOISE, true, SPLIT_FIRST>(sa, sx, sy, &ring);
+    }
+    if (second && a.parts) {
+        DiagAcc acc{0.0, 0.0, -1.0, 0.0};
+        strip_diag<R, T>(sa, sx, sy, acc);
+        const double sb = wave_sum64(acc.sb), sn = wave_sum64(acc.sn);
+        const double m2 = wave_max64(acc.m2), ct = wave_sum64(acc.cnt);
+        if ((threadIdx.x & 63) == 0) {
+            double *q = a.parts + 4 * (size_t)strip;
+            q[0] = sb;
+            q[1] = sn;
+            q[2] = m2;
+            q[3] = ct;
+        }
+    }
+}
+
 // The compiled fused kernel of precision R, integrator RK and noise mode NOISE
-// for (law, levels, prefetch), or null when there is none.  Each (R, RK,
-// NOISE) triple is defined in a translation unit of its own
+// for (law, levels, prefetch, waves per strip), or null when there is none.
+// Each (R, RK, NOISE) triple is defined in a translation unit of its own
 // (kc_stream_<precision>_<integrator>[_noise].hip).
 template <typename R, bool RK, bool NOISE>
-const void *stream_kernel_for(int chi_law, int levels, int pf);
+const void *stream_kernel_for(int chi_law, int levels, int pf, int waves);
+
+// Kernel table of one (R, RK, NOISE) triple: whole-strip kernels for levels
+// {1, 2, 3, 4, 6, 8} (forward Euler) or {2, 4, 6} (Runge-Kutta), split kernels
+// for the even level counts whose halves are whole time steps ({2, 4, 6, 8} and
+// {4}), prefetch depth 2 or 4.
+template <typename R, int T, int LAW, bool RK, bool NOISE>
+const void *pick_kernel(int pf, int waves)
+{
+    constexpr bool can_split = T % 2 == 0 && (!RK || (T / 2) % 2 == 0);
+    if (waves == 2) {
+        if constexpr (can_split)
+            return pf == 4 ? reinterpret_cast<const void *>(&step_split<R, T, LAW, 4, RK, NOISE>)
+                           : reinterpret_cast<const void *>(&step_split<R, T, LAW, 2, RK, NOISE>);
+        return nullptr;
+    }
+    return pf == 4 ? reinterpret_cast<const void *>(&step_stream<R, T, LAW, 4, RK, NOISE>)
+                   : reinterpret_cast<const void *>(&step_stream<R, T, LAW, 2, RK, NOISE>);
+}
+
+template <typename R, int LAW, bool RK, bool NOISE>
+const void *pick_levels(int levels, int pf, int waves)
+{
+    if constexpr (RK) {
+        switch (levels) {
+        case 2: return pick_kernel<R, 2, LAW, RK, NOISE>(pf, waves);
+        case 4: return pick_kernel<R, 4, LAW, RK, NOISE>(pf, waves);
+        case 6: return pick_kernel<R, 6, LAW, RK, NOISE>(pf, waves);
+        default: return nullptr;
+        }
+    } else {
+        switch (levels) {
+        case 1: return pick_kernel<R, 1, LAW, RK, NOISE>(pf, waves);
+        case 2: return pick_kernel<R, 2, LAW, RK, NOISE>(pf, waves);
+        case 3: return pick_kernel<R, 3, LAW, RK, NOISE>(pf, waves);
+        case 4: return pick_kernel<R, 4, LAW, RK, NOISE>(pf, waves);
+        case 6: return pick_kernel<R, 6, LAW, RK, NOISE>(pf, waves);
+        case 8: return pick_kernel<R, 8, LAW, RK, NOISE>(pf, waves);
+        default: return nullptr;
+        }
+    }
+}
+
+template <typename R, bool RK, bool NOISE>
+const void *stream_kernel_table(int chi_law, int levels, int pf, int waves)
+{
+    if ((pf != 2 && pf != 4) || (waves != 1 && waves != 2))
+        return nullptr;
+    return chi_law == 0 ? pick_levels<R, 0, RK, NOISE>(levels, pf, waves)
+                        : pick_levels<R, 1, RK, NOISE>(levels, pf, waves);
+}
 
 } // namespace kc

@@ -155,11 +155,30 @@ __device__ __forceinline__ bool strip_inside(const StripArgs<R> &a, int sx)
     return xl >= 0 && xl + WC <= a.nx;
 }
 
+// Roles of a wavefront in a strip: the whole block of T levels (WHOLE), or
+// half of it with the other half in a second wavefront of the same workgroup
+// (SPLIT_FIRST: levels [0, T/2), input rows from memory, its last level's rows
+// handed over through a ring of LDS slots; SPLIT_SECOND: levels [T/2, T),
+// input rows from that ring, output rows to memory).
+enum { WHOLE = 0, SPLIT_FIRST = 1, SPLIT_SECOND = 2 };
+
+// LDS ring between the two wavefronts of a split strip: 2 PF row slots of b
+// and n (two groups of PF rows, double-buffered), 64 lanes of VEC cells each.
+template <typename R, int PF> struct SplitRing {
+    typedef typename VecT<R, StreamShape<R>::VEC>::type vec_t;
+    vec_t v[2 * PF][2][64];
+};
+
 template <typename R, int T, int LAW, int PF, bool EDGE, bool RK = false, bool NOISE = false,
-          bool GEN = false>
-__device__ __forceinline__ void stream_strip(const StripArgs<R> &a, int sx, int sy)
+          bool GEN = false, int ROLE = WHOLE>
+__device__ __forceinline__ void stream_strip(const StripArgs<R> &a, int sx, int sy,
+                                             SplitRing<R, PF> *ring = nullptr)
 {
     static_assert(!RK || T % 2 == 0, "a two-stage Runge-Kutta block has an even level count");
+    static_assert(ROLE == WHOLE || (T % 2 == 0 && (!RK || (T / 2) % 2 == 0)),
+                  "a split strip hands over whole time steps");
+    constexpr int L0 = ROLE == SPLIT_SECOND ? T / 2 : 0; // first level of this wavefront
+    constexpr int L1 = ROLE == SPLIT_FIRST ? T / 2 : T;  // one past its last level
     constexpr int VEC = StreamShape<R>::VEC;
     constexpr int HX = Halo<T, VEC>::HX;
     constexpr int WC = Halo<T, VEC>::WC;
@@ -259,13 +278,35 @@ __device__ __forceinline__ void stream_strip(const StripArgs<R> &a, int sx, int 
     };
     // time step (after the launch's first) that level L advances
     auto level_step = [](int L) { return RK ? L / 2 : L; };
+    // the second wavefront of a split strip loads only sigma (static field),
+    // for its incoming rows (row - L0 at iteration row)
+    auto load_sigma = [&](int row, vec_t &vs, auto full_tag) __attribute__((always_inline)) {
+        if constexpr (!NOISE) {
+            const size_t base = (size_t)mrow(row, full_tag) * a.pitch;
+            const int nbytes = a.pitch * (int)sizeof(R);
+            const __amdgpu_buffer_rsrc_t rsg = row_rsrc(a.sg + base, nbytes);
+            if constexpr (!EDGE) {
+                vs = buf_load16<vec_t>(rsg, (uint32_t)x0 * (uint32_t)sizeof(R));
+            } else {
 #pragma unroll
-    for (int u = 0; u < PF; ++u)
-        load_row(rs + u, pb[u], pn[u], ps[u], BoolTag<false>());
+                for (int k = 0; k < VEC; ++k)
+                    vs[k] = buf_load<R>(rsg, (uint32_t)xm[k] * (uint32_t)sizeof(R));
+            }
+        } else {
+            vs = vec_t{};
+        }
+    };
+#pragma unroll
+    for (int u = 0; u < PF; ++u) {
+        if constexpr (ROLE == SPLIT_SECOND)
+            load_sigma(rs - L0 + u, ps[u], BoolTag<false>());
+        else
+            load_row(rs + u, pb[u], pn[u], ps[u], BoolTag<false>());
+    }
 
     // One group of PF rows.  With FULL every level is active on every row of
     // the group (the steady state), so the body is one straight-line block.
-    auto group = [&](int r0, auto full_tag) {
+    auto group = [&](int r0, int slot0, auto full_tag) {
         constexpr bool FULL = decltype(full_tag)::value;
 #pragma unroll
         for (int u = 0; u < PF; ++u) {
@@ -273,22 +314,38 @@ __device__ __forceinline__ void stream_strip(const StripArgs<R> &a, int sx, int 
             // consume slot u (row), refill it with row + PF
             R ib[VEC], in[VEC], iD[VEC], iX[VEC], is[VEC];
             R iub[VEC], iun[VEC]; // RK: u of the incoming row of an odd level
+            if constexpr (ROLE == SPLIT_SECOND) {
+                // incoming row of level L0: what the first wavefront handed over
+                const vec_t vb = ring->v[slot0 + u][0][lane];
+                const vec_t vn = ring->v[slot0 + u][1][lane];
 #pragma unroll
-            for (int k = 0; k < VEC; ++k) {
-                ib[k] = pb[u][k];
-                in[k] = pn[u][k];
-                is[k] = R(0.5) * ps[u][k];
-                iub[k] = iun[k] = R(0);
+                for (int k = 0; k < VEC; ++k) {
+                    ib[k] = vb[k];
+                    in[k] = vn[k];
+                    is[k] = R(0.5) * ps[u][k];
+                    iub[k] = iun[k] = R(0);
+                }
+                if (NOISE) // sigma of row - L0 at the step of level L0
+                    draw(level_step(L0), row - L0, is, full_tag);
+                load_sigma(row - L0 + PF, ps[u], full_tag);
+            } else {
+#pragma unroll
+                for (int k = 0; k < VEC; ++k) {
+                    ib[k] = pb[u][k];
+                    in[k] = pn[u][k];
+                    is[k] = R(0.5) * ps[u][k];
+                    iub[k] = iun[k] = R(0);
+                }
+                if (NOISE) // sigma of the incoming row at the first level's step
+                    draw(level_step(0), row, is, full_tag);
+                load_row(row + PF, pb[u], pn[u], ps[u], full_tag);
             }
-            if (NOISE) // sigma of the incoming row at the first level's step
-                draw(level_step(0), row, is, full_tag);
-            load_row(row + PF, pb[u], pn[u], ps[u], full_tag);
 #pragma unroll
             for (int k = 0; k < VEC; ++k)
                 coef<R, LAW>(is[k], in[k], ib[k], a.c.chi2, iD[k], iX[k]);
 
 #pragma unroll
-            for (int L = 0; L < T; ++L) {
+            for (int L = L0; L < L1; ++L) {
                 const int y = row - L - 1; // centre row of this level
                 if (!FULL && (y < y0 - T + L || y >= y1 + T - 1 - L)) {
                     // outside this level's rows: only move the incoming row in
@@ -362,7 +419,7 @@ __device__ __forceinline__ void stream_strip(const StripArgs<R> &a, int sx, int 
                     cX[L][k] = iX[k];
                     cs[L][k] = is[k];
                 }
-                if (L + 1 < T) {
+                if (L + 1 < L1) {
                     if (NOISE && level_step(L + 1) != level_step(L)) {
                         // the next level advances a later step: fresh sigma of row y
                         draw(level_step(L + 1), y, os, full_tag);
@@ -373,6 +430,14 @@ __device__ __forceinline__ void stream_strip(const StripArgs<R> &a, int sx, int 
                         in[k] = on[k];
                         is[k] = os[k];
                         coef<R, LAW>(is[k], in[k], ib[k], a.c.chi2, iD[k], iX[k]);
+                    }
+                } else if (L1 < T) {
+                    // the next level runs in the second wavefront: hand over b, n of
+                    // row y (it takes sigma and the coefficients itself)
+#pragma unroll
+                    for (int k = 0; k < VEC; ++k) {
+                        ib[k] = ob[k];
+                        in[k] = on[k];
                     }
                 } else if (y >= y0 && y < y1 && lane_out) {
                     vec_t vb, vn;
@@ -388,6 +453,37 @@ __device__ __forceinline__ void stream_strip(const StripArgs<R> &a, int sx, int 
                     buf_store16<vec_t>(vn, row_rsrc(a.n_out + rowp, nbytes), o);
                 }
             }
+            if constexpr (ROLE == SPLIT_FIRST) {
+                // the incoming row of level L1 (computed, or passed through where
+                // the last level skipped this row) into the ring
+                vec_t vb, vn;
+#pragma unroll
+                for (int k = 0; k < VEC; ++k) {
+                    vb[k] = ib[k];
+                    vn[k] = in[k];
+                }
+                ring->v[slot0 + u][0][lane] = vb;
+                ring->v[slot0 + u][1][lane] = vn;
+            }
+        }
+    };
+    // Split strips: the first wavefront writes group g into ring half g % 2 and
+    // then meets the second at a barrier; the second meets it there before
+    // reading group g.  Both walk the same groups, so both pass the same number
+    // of barriers, and a half is rewritten only after the barrier that follows
+    // its last read.
+    auto run_group = [&](int r0, auto full_tag) __attribute__((always_inline)) {
+        const int slot0 = ((((r0 - rs) / PF) & 1) != 0) ? PF : 0;
+        if constexpr (ROLE == SPLIT_SECOND) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            __builtin_amdgcn_s_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        }
+        group(r0, slot0, full_tag);
+        if constexpr (ROLE == SPLIT_FIRST) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            __builtin_amdgcn_s_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
         }
     };
 
@@ -401,11 +497,11 @@ __device__ __forceinline__ void stream_strip(const StripArgs<R> &a, int sx, int 
     const bool steady_ok = a.ny >= T + PF;
     int r0 = rs;
     for (; r0 < re && r0 < full_lo; r0 += PF)
-        group(r0, BoolTag<false>());
+        run_group(r0, BoolTag<false>());
     for (; steady_ok && r0 + PF <= re; r0 += PF)
-        group(r0, BoolTag<true>());
+        run_group(r0, BoolTag<true>());
     for (; r0 < re; r0 += PF)
-        group(r0, BoolTag<false>());
+        run_group(r0, BoolTag<false>());
 }
 
 // Diagnostics of the output block of strip (sx, sy) after stream_strip<.., T, ..>

@@ -1,7 +1,9 @@
 // kc_tune.hip -- autotuner cache (host side).
 //
 // Cache file: one JSON object per line,
-//   {"key": "<arch>|<nx>x<ny>|fp32|receptor", "tsteps": T, "rows": R, "prefetch": P, "gcell_s": G}
+//   {"key": "<arch>|<nx>x<ny>|fp32|receptor", "tsteps": T, "rows": R, "prefetch": P,
+//    "waves": W, "gcell_s": G}
+// (an entry without "waves" has one wavefront per strip)
 // The path comes from the environment variable KC_AUTOTUNE_CACHE; without it
 // nothing is read or written.  A later line with the same key wins.
 #include <stdio.h>
@@ -36,7 +38,7 @@ int device_key(char *buf, size_t n, int nx, int ny, int precision, int chi_law, 
 
 static const char *cache_path() { return getenv("KC_AUTOTUNE_CACHE"); }
 
-bool cache_lookup(const char *key, int integrator, Tuning *t)
+bool cache_lookup(const char *key, int integrator, Tuning *t, double *gcells)
 {
     const char *path = cache_path();
     if (!path || !*path)
@@ -50,16 +52,26 @@ bool cache_lookup(const char *key, int integrator, Tuning *t)
     while (fgets(line, sizeof line, f)) {
         if (!strstr(line, want.c_str()))
             continue;
-        int T = 0, R = 0, P = 0;
+        int T = 0, R = 0, P = 0, W = 1;
         const char *pt = strstr(line, "\"tsteps\":");
         const char *pr = strstr(line, "\"rows\":");
         const char *pp = strstr(line, "\"prefetch\":");
+        const char *pw = strstr(line, "\"waves\":");
+        if (pw && sscanf(pw, "\"waves\": %d", &W) != 1)
+            W = 1;
         if (pt && pr && pp && sscanf(pt, "\"tsteps\": %d", &T) == 1 &&
             sscanf(pr, "\"rows\": %d", &R) == 1 && sscanf(pp, "\"prefetch\": %d", &P) == 1 &&
-            T >= 1 && T <= 8 && R >= 1 && (P == 2 || P == 4)) {
+            T >= 1 && T <= 8 && R >= 1 && (P == 2 || P == 4) && (W == 1 || W == 2)) {
             t->tsteps = stream_depth_at_most(T, integrator);
             t->rows = R;
             t->prefetch = P;
+            t->waves = W;
+            double g = 0.0;
+            const char *pg = strstr(line, "\"gcell_s\":");
+            if (pg && sscanf(pg, "\"gcell_s\": %lf", &g) != 1)
+                g = 0.0;
+            if (gcells)
+                *gcells = g;
             found = true;
         }
     }
@@ -75,8 +87,10 @@ void cache_store(const char *key, const Tuning &t, double gcells)
     FILE *f = fopen(path, "a");
     if (!f)
         return;
-    fprintf(f, "{\"key\": \"%s\", \"tsteps\": %d, \"rows\": %d, \"prefetch\": %d, \"gcell_s\": %.3f}\n",
-            key, t.tsteps, t.rows, t.prefetch, gcells);
+    fprintf(f,
+            "{\"key\": \"%s\", \"tsteps\": %d, \"rows\": %d, \"prefetch\": %d, \"waves\": %d, "
+            "\"gcell_s\": %.3f}\n",
+            key, t.tsteps, t.rows, t.prefetch, t.waves, gcells);
     fclose(f);
 }
 

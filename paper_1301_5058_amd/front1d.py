@@ -2,10 +2,11 @@
 
 For every (n0, chi0) of the experiment one 1 x cells grid on [0, length] runs
 the system velo-system-1d (constant sensitivity, sigma = sigma0): all
-instances in one batch (kb_* calls, per-block launches), the front position
-sampled on the device as the envelope radius about x = 0 (centre at cell
-index -1/2, threshold b_thr = n0 / 2), and its velocity fitted on the device
-over the window of front positions.  The velocities are compared with the
+instances in one batch (kb_* calls), the front position sampled on the device
+as the envelope radius about x = 0 (centre at cell index -1/2, threshold
+b_thr = min(0.5, n0 / 2): the paper's "vicinity of 0.5", below the plateau n0
+for poor nutrient), and its velocity fitted on the device over the window of
+front positions.  The velocities are compared with the
 closed-form bound c-bar(n0, chi0) of Sec. 4.1 (ks_cbar) and with the threshold
 speed c* of the scalar front equation (ks_cstar); the speeds over the
 two halves of the window tell a steady front from one that still changes
@@ -39,7 +40,8 @@ def instances(cells=None, n0s=None, chis=None):
             b, n, s = workload.front1d_fields(cells, c["length"], n0, c["b_max"], c["r0"], c["cut"],
                                               c["sigma0"])
             dt = workload.front1d_dt(cells, c["length"], n0, chi, c["b_max"], c["sigma0"])
-            descs.append(dict(nx=cells, ny=1, h=h, dt=dt, chi=float(chi), b_thr=0.5 * n0,
+            descs.append(dict(nx=cells, ny=1, h=h, dt=dt, chi=float(chi),
+                              b_thr=workload.front1d_threshold(n0, c["threshold"]),
                               cx=-0.5, cy=0.0, n0=float(n0)))
             fields.append((b, n, s))
     return descs, fields

@@ -65,6 +65,8 @@ _SIGS = {
     "kc_check_step": (c_int32, [c_int32, c_int32, c_int32, c_void_p, c_void_p, c_void_p, c_double,
                                 c_double, ctypes.POINTER(KcParams), P_double]),
     "kc_set_tuning": (c_int32, [c_void_p, c_int32, c_int32, c_int32]),
+    "kc_set_strip_waves": (c_int32, [c_void_p, c_int32]),
+    "kc_get_strip_waves": (c_int32, [c_void_p, ctypes.POINTER(c_int32)]),
     "kc_get_tuning": (c_int32, [c_void_p, ctypes.POINTER(c_int32), ctypes.POINTER(c_int32),
                                 ctypes.POINTER(c_int32)]),
     "kc_set_reference_kernel": (c_int32, [c_void_p, c_int32]),

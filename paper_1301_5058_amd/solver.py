@@ -145,8 +145,16 @@ class Solver:
         return t.value, s.value
 
     # -- kernel configuration ---------------------------------------------------
-    def set_tuning(self, tsteps=0, rows=0, prefetch=0):
+    def set_tuning(self, tsteps=0, rows=0, prefetch=0, waves=0):
+        """waves: wavefronts per strip (1 or 2; 0 keeps the current value)."""
         N.check(N.lib().kc_set_tuning(self.ctx, int(tsteps), int(rows), int(prefetch)), self.ctx)
+        if waves:
+            N.check(N.lib().kc_set_strip_waves(self.ctx, int(waves)), self.ctx)
+
+    def strip_waves(self):
+        w = ctypes.c_int32()
+        N.check(N.lib().kc_get_strip_waves(self.ctx, ctypes.byref(w)))
+        return w.value
 
     def tuning(self):
         t, r, p = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()

@@ -51,8 +51,8 @@ def main():
                    noise=noise)
         S.set_fields(*(torch.from_numpy(x).cuda() for x in ((b, n) if noise else (b, n, s))))
         g = S.autotune(effort=a.effort, use_cache=True)
-        print("%5d^2 %s %s: tsteps=%d rows=%d prefetch=%d  %.1f GCell/s"
-              % ((nx, prec, integ) + S.tuning() + (g,)), flush=True)
+        print("%5d^2 %s %s: tsteps=%d rows=%d prefetch=%d waves/strip=%d  %.1f GCell/s"
+              % ((nx, prec, integ) + S.tuning() + (S.strip_waves(), g)), flush=True)
         S.close()
     return 0
 

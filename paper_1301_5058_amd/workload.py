@@ -92,12 +92,19 @@ def sweep(count=256, meta_seed=2026, sides=(256, 512, 1024, 2048)):
 # {0, 1, 2.5, 5, 10} (constant sensitivity).  Readings: cell-centred cells
 # x_i = (i + 1/2) h on [0, length]; the inoculum is cut beyond 3 r0 (r0 = 2.5),
 # as in two dimensions, because logistic growth of an uncut tail would reach
-# the threshold ahead of the front; the front position is fitted over
+# the threshold ahead of the front; the front is the largest x with
+# b >= min(0.5, n0 / 2) (the paper tracks a point "in the vicinity of 0.5";
+# n0 / 2 where the plateau n0 stays below it), and its speed is fitted over
 # x in [9, 17], beyond the initial support.
 # ---------------------------------------------------------------------------
 FRONT1D = dict(length=20.0, cells=400, b_max=0.71, r0=2.5, cut=3.0, sigma0=1.0,
                n0=(0.35, 0.71, 1.07, 2.0, 3.0, 4.0), chi=(0.0, 1.0, 2.5, 5.0, 10.0),
-               window=(9.0, 17.0))
+               window=(9.0, 17.0), threshold=0.5)
+
+
+def front1d_threshold(n0, level=0.5):
+    """Front threshold of the 1-D experiment: `level`, or n0 / 2 when smaller."""
+    return min(level, 0.5 * n0)
 
 
 def front1d_fields(cells, length, n0, b_max=0.71, r0=2.5, cut=3.0, sigma0=1.0):

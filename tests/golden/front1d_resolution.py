@@ -7,7 +7,8 @@ For each (n0, chi0) below and each grid of `cells` cells on [0, 20] the oracle
 runs the experiment's set-up (constant sensitivity, sigma = 1, the cut
 inoculum 0.71 exp(-x^2 / 6.25), forward Euler at the experiment's time step
 0.2 h^2 / max(D_n, sigma0 n0 (n0 + b_M)(1 + chi0 n0)), which scales with h^2)
-and samples the front position -- the largest x of a cell with b >= n0 / 2 --
+and samples the front position -- the largest x of a cell with
+b >= min(0.5, n0 / 2) --
 at the same physical times on every grid (every 100 steps of the 400-cell
 grid).  A run stops once the front has passed x = 17.5 or at the time a front
 moving at a quarter of the bound c-bar of Sec. 4.1 needs to cross [7.5, 17].
@@ -80,7 +81,7 @@ def run_one(args):
         b, n = oracle.run(b, n, s, h, dt, every, chi=chi, chi_law=1)
         k += every
         t = k * dt
-        r = oracle.diag(b, n, h, 0.5 * n0, cx=-0.5, cy=0.0)[2]
+        r = oracle.diag(b, n, h, min(0.5, 0.5 * n0), cx=-0.5, cy=0.0)[2]
         ts.append(t)
         rs.append(r)
         if r >= WINDOW[1] + 0.5 or t >= t_end:

@@ -73,7 +73,8 @@ def test_noise_small_workload_fp32_matches_oracle():
 
 
 SHAPES = [(128, 128), (257, 31), (64, 1), (1, 40), (300, 97)]
-TUNINGS = [(1, 1, 2), (2, 7, 4), (3, 16, 2), (4, 35, 4), (8, 3, 4), (6, 1000, 2)]
+TUNINGS = [(1, 1, 2), (2, 7, 4), (3, 16, 2), (4, 35, 4), (8, 3, 4), (6, 1000, 2),
+           (2, 7, 4, 2), (4, 35, 2, 2), (8, 3, 2, 2)]
 
 
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
@@ -84,7 +85,8 @@ def test_noise_fused_launches_bitwise_equal_to_reference(precision, nx, ny):
     b = np.maximum(b, rng.uniform(0, 0.3, b.shape).astype(np.float32) *
                    (rng.uniform(size=b.shape) < 0.3))
     dt = 0.08
-    for integ, tunes in (("euler", TUNINGS), ("rk2", [(1, 5, 2), (2, 9, 4), (3, 100, 4)])):
+    for integ, tunes in (("euler", TUNINGS),
+                         ("rk2", [(1, 5, 2), (2, 9, 4), (3, 100, 4), (2, 19, 2, 2), (2, 4, 4, 2)])):
         rb, rn = _run(b, n, 11, dt, precision=precision, ref=True, integrator=integ, chi=1.3)
         for t in tunes:
             gb, gn = _run(b, n, 11, dt, precision=precision, tuning=t, integrator=integ, chi=1.3)

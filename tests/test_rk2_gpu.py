@@ -52,7 +52,8 @@ def test_rk2_differs_from_euler():
 
 
 SHAPES = [(128, 128), (700, 150), (257, 31), (1, 64), (64, 1), (5, 3), (300, 97)]
-TUNINGS = [(1, 1, 2), (1, 9, 4), (2, 7, 4), (2, 35, 2), (3, 16, 4), (3, 3, 2), (4, 1000, 4)]
+TUNINGS = [(1, 1, 2), (1, 9, 4), (2, 7, 4), (2, 35, 2), (3, 16, 4), (3, 3, 2), (4, 1000, 4),
+           (2, 7, 2, 2), (2, 19, 4, 2), (2, 1000, 2, 2), (1, 5, 2, 2)]
 
 
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])

@@ -39,7 +39,7 @@ def _solver(nx, ny, precision, integrator, noise, tuning):
 
 
 CASES = [("euler", (4, 35, 4)), ("euler", (3, 7, 2)), ("euler", (8, 16, 4)), ("euler", (1, 1, 4)),
-         ("rk2", (2, 9, 4)), ("rk2", (3, 100, 2))]
+         ("rk2", (2, 9, 4)), ("rk2", (3, 100, 2)), ("euler", (4, 35, 2, 2)), ("rk2", (2, 9, 4, 2))]
 
 
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
