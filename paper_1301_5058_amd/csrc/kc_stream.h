@@ -495,13 +495,36 @@ __device__ __forceinline__ void stream_strip(const StripArgs<R> &a, int sx, int 
     // group as a tail group.
     const int full_lo = y0 + T - 1;
     const bool steady_ok = a.ny >= T + PF;
+    // Wavefronts that share a SIMD issue oldest first, so the first strip
+    // dispatched to a SIMD would finish long before the second, which then
+    // runs alone at single-wavefront issue rate.  The strip's issue priority
+    // instead falls in four steps as it advances (3 on its first quarter of
+    // groups, 0 on its last): a wavefront that is ahead yields to one that is
+    // behind, and the strips of a SIMD end nearly together.
+    const int q1 = rs + (re - rs) / 4, q2 = rs + (re - rs) / 2, q3 = rs + 3 * (re - rs) / 4;
+    auto set_priority = [&](int r0) __attribute__((always_inline)) {
+        if (r0 >= q3)
+            __builtin_amdgcn_s_setprio(0);
+        else if (r0 >= q2)
+            __builtin_amdgcn_s_setprio(1);
+        else if (r0 >= q1)
+            __builtin_amdgcn_s_setprio(2);
+        else
+            __builtin_amdgcn_s_setprio(3);
+    };
     int r0 = rs;
-    for (; r0 < re && r0 < full_lo; r0 += PF)
+    for (; r0 < re && r0 < full_lo; r0 += PF) {
+        set_priority(r0);
         run_group(r0, BoolTag<false>());
-    for (; steady_ok && r0 + PF <= re; r0 += PF)
+    }
+    for (; steady_ok && r0 + PF <= re; r0 += PF) {
+        set_priority(r0);
         run_group(r0, BoolTag<true>());
-    for (; r0 < re; r0 += PF)
+    }
+    for (; r0 < re; r0 += PF) {
+        set_priority(r0);
         run_group(r0, BoolTag<false>());
+    }
 }
 
 // Diagnostics of the output block of strip (sx, sy) after stream_strip<.., T, ..>

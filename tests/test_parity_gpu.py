@@ -366,6 +366,7 @@ def test_autotune_keeps_state_and_caches(tmp_path, monkeypatch):
     assert np.array_equal(gb, ref_b) and np.array_equal(gn, ref_n)
     assert cache.read_text().count('"key"') == 1
     S.set_tuning(1, 8, 2)
-    assert S.autotune(effort=0, use_cache=True) == 0.0  # answered by the cache
+    # answered by the cache: the tuning and the rate stored with it
+    assert S.autotune(effort=0, use_cache=True) == round(g, 3)
     assert S.tuning() == t1
     S.close()
