@@ -217,10 +217,11 @@ __device__ __forceinline__ void stream_strip(const StripArgs<R> &a, int sx, int 
             cb[L][k] = cn[L][k] = cD[L][k] = cX[L][k] = cs[L][k] = fb[L][k] = fn[L][k] =
                 cub[L][k] = cun[L][k] = R(0);
 
-    // Prefetch ring: slot (row - rs) % PF.  Rows are reflected into the grid
-    // (rows past re are loaded and never used); interior strips load one
-    // 16-byte vector per field, edge strips one cell at a time from the
-    // mirrored columns.
+    // Prefetch ring: slot (row - rs) % PF.  Rows are reflected into the grid;
+    // rows past the strip's last input row re - 1 are never used and load row
+    // re - 1 again (a cache hit) instead of the next strip's rows; interior
+    // strips load one 16-byte vector per field, edge strips one cell at a time
+    // from the mirrored columns.
     // In the steady state (FULL groups) every row is >= 0 and below 2 ny, so one
     // branch-free reflection suffices; the lead-in and tail groups reflect in
     // general.
@@ -299,9 +300,9 @@ __device__ __forceinline__ void stream_strip(const StripArgs<R> &a, int sx, int 
 #pragma unroll
     for (int u = 0; u < PF; ++u) {
         if constexpr (ROLE == SPLIT_SECOND)
-            load_sigma(rs - L0 + u, ps[u], BoolTag<false>());
+            load_sigma(min(rs - L0 + u, re - 1 - L0), ps[u], BoolTag<false>());
         else
-            load_row(rs + u, pb[u], pn[u], ps[u], BoolTag<false>());
+            load_row(min(rs + u, re - 1), pb[u], pn[u], ps[u], BoolTag<false>());
     }
 
     // One group of PF rows.  With FULL every level is active on every row of
@@ -327,7 +328,7 @@ __device__ __forceinline__ void stream_strip(const StripArgs<R> &a, int sx, int 
                 }
                 if (NOISE) // sigma of row - L0 at the step of level L0
                     draw(level_step(L0), row - L0, is, full_tag);
-                load_sigma(row - L0 + PF, ps[u], full_tag);
+                load_sigma(min(row - L0 + PF, re - 1 - L0), ps[u], full_tag);
             } else {
 #pragma unroll
                 for (int k = 0; k < VEC; ++k) {
@@ -338,7 +339,7 @@ __device__ __forceinline__ void stream_strip(const StripArgs<R> &a, int sx, int 
                 }
                 if (NOISE) // sigma of the incoming row at the first level's step
                     draw(level_step(0), row, is, full_tag);
-                load_row(row + PF, pb[u], pn[u], ps[u], full_tag);
+                load_row(min(row + PF, re - 1), pb[u], pn[u], ps[u], full_tag);
             }
 #pragma unroll
             for (int k = 0; k < VEC; ++k)
