@@ -133,6 +133,7 @@ def cpu_baseline(b, n, s, dt, chi, budget_s=15.0):
     same 4096^2 fields (calibrated to ~budget_s of CPU time)."""
     import numpy as np
     import oracle
+    build = oracle.use_native()  # the same arithmetic, built for this host's CPU
     b64, n64, s64 = (a.astype(np.float64) for a in (b, n, s))
     t0 = time.perf_counter()
     oracle.run(b64, n64, s64, 1.0, dt, 2, chi=chi)
@@ -165,6 +166,7 @@ def cpu_baseline(b, n, s, dt, chi, budget_s=15.0):
             "cores": cores, "kind": "oracle",
             "sample": "FP64 C oracle, %d steps of the same %dx%d fields (%.1f s)"
                       % (steps, b.shape[1], b.shape[0], el),
+            "build": build,
             "single_thread": {"value": round(cells * steps1 / el1 / 1e9, 5), "steps": steps1,
                               "seconds": round(el1, 2)},
             "host": {"cpu_model": model, "nproc": os.cpu_count()}}
@@ -505,20 +507,52 @@ def front1d_speeds():
     from paper_1301_5058_amd import front1d
     r = front1d.run_front1d()
     v1, v2 = r["velocity_halves"]
+    spread = resolution_spread(r["cells"])
     # "steady": the speeds over the two halves of the window agree within 10 %
     # (a travelling front); otherwise the window speed is the mean of a
     # transient (strong chemotaxis bursts ahead and decelerates, poor nutrient
-    # stalls).  "above_cbar": faster than c-bar by more than the 1.5 % that the
-    # oracle's 400 -> 3200-cell resolution study moves any speed.
-    rows = [{"n0": p[0], "chi0": p[1], "v": round(float(v), 5), "steady": bool(st),
-             "v_halves": [round(float(a), 5), round(float(b), 5)],
-             "above_cbar": bool(v > 1.015 * cb),
-             "cbar": round(float(cb), 5), "cstar": round(float(cs), 5),
-             "v_over_cbar": round(float(v / cb), 4), "v_over_cstar": round(float(v / cs), 4)}
-            for p, v, st, a, b, cb, cs in zip(r["points"], r["velocity"], r["steady"], v1, v2,
-                                              r["cbar"], r["cstar"])]
+    # stalls).  "resolution_spread": how far the FP64 oracle's speed on this
+    # grid lies from its speed on the finest grid of its resolution study
+    # (tests/golden/front1d_resolution.txt; null where the study has no row);
+    # "resolved": that spread is below 2 %.  "above_cbar": faster than c-bar
+    # by more than that spread plus the 1 % FP32 / FP64 bar.
+    rows = []
+    for p, v, st, a, b, cb, cs, te in zip(r["points"], r["velocity"], r["steady"], v1, v2,
+                                          r["cbar"], r["cstar"], r["t_end"]):
+        sp = spread.get((round(p[0], 2), round(p[1], 1)))
+        rows.append({"n0": p[0], "chi0": p[1], "v": round(float(v), 5), "steady": bool(st),
+                     "v_halves": [round(float(a), 5), round(float(b), 5)],
+                     "t_end": round(float(te), 5),
+                     "resolution_spread": None if sp is None else round(sp, 5),
+                     "resolved": None if sp is None else bool(sp <= 0.02),
+                     "above_cbar": bool(v > cb * (1.0 + 0.01 + (sp or 0.0))),
+                     "cbar": round(float(cb), 5), "cstar": round(float(cs), 5),
+                     "v_over_cbar": round(float(v / cb), 4),
+                     "v_over_cstar": round(float(v / cs), 4)})
     return {"cells": r["cells"], "steps": r["steps"], "window": list(r["window"]),
             "gpu_s": round(r["gpu_s"], 3), "wall_s": round(r["wall_s"], 3), "fronts": rows}
+
+
+def resolution_spread(cells):
+    """{(n0, chi0): |v(cells) - v(finest)| / v(finest)} from the oracle's
+    resolution study of the 1-D experiment (a text table in tests/golden)."""
+    path = os.path.join(ROOT, "tests", "golden", "front1d_resolution.txt")
+    tab = {}
+    try:
+        for line in open(path):
+            if line.startswith("#") or not line.strip():
+                continue
+            f = line.split()
+            tab.setdefault((round(float(f[0]), 2), round(float(f[1]), 1)), {})[int(f[2])] = \
+                float(f[7])
+    except OSError:
+        return {}
+    out = {}
+    for key, by_cells in tab.items():
+        finest = max(by_cells)
+        if cells in by_cells and finest > cells and by_cells[finest] > 0:
+            out[key] = abs(by_cells[cells] - by_cells[finest]) / by_cells[finest]
+    return out
 
 
 def main():

@@ -98,6 +98,14 @@ enum { KB_RADIUS_ENVELOPE = 0, KB_RADIUS_AREA = 1 };
 int kb_fit_velocity(kb_batch *bt, int32_t radius, const double *r_lo, const double *r_hi,
                     double *v, int32_t *npoints);
 
+/* kb_fit_velocity over the samples recorded at times t <= t_max[k] only
+ * (t_max: host array of count doubles, +infinity for no limit, or NULL for
+ * none at all; a NaN entry is KC_EINVAL): the fit of a run cut at its own end
+ * time, e.g. the 1-D experiment of Sec. 4.2, whose slow fronts stall long
+ * before the batch's last step. */
+int kb_fit_velocity_until(kb_batch *bt, int32_t radius, const double *r_lo, const double *r_hi,
+                          const double *t_max, double *v, int32_t *npoints);
+
 /* Kernel configuration.  tsteps: steps per time block (a compiled depth that
  * divides sample_every is used); rows: output rows per strip for each
  * instance (count entries, or NULL to keep); prefetch 2 or 4 (0 keeps);

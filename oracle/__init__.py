@@ -20,8 +20,10 @@ Contents
   mlp_ref             FP64 forward / backward of the velocity surrogate MLP.
 """
 import ctypes
+import hashlib
 import os
 import subprocess
+import tempfile
 
 import numpy as np
 
@@ -34,57 +36,86 @@ CHI_RECEPTOR = 0
 CHI_CONSTANT = 1
 
 
-def build(force=False):
-    """Compile kc_oracle.c with gcc (-O3, OpenMP, no FMA contraction)."""
-    if not force and os.path.exists(_LIB_PATH) and \
-            os.path.getmtime(_LIB_PATH) >= os.path.getmtime(_SRC):
-        return _LIB_PATH
-    tmp = _LIB_PATH + ".tmp%d" % os.getpid()
-    cmd = ["gcc", "-O3", "-fopenmp", "-ffp-contract=off", "-fPIC", "-shared",
-           "-std=c99", "-o", tmp, _SRC, "-lm"]
+FLAGS = ["-O3", "-fopenmp", "-ffp-contract=off", "-fPIC", "-shared", "-std=c99"]
+
+
+def _native_path():
+    """Per-host path of the -march=native build (never shipped with the tree:
+    another machine's CPU may lack the instructions)."""
+    h = hashlib.sha256()
+    with open(_SRC, "rb") as f:
+        h.update(f.read())
+    try:
+        with open("/proc/cpuinfo") as f:
+            h.update("".join(ln for ln in f if ln.startswith(("model name", "flags"))).encode())
+    except OSError:
+        pass
+    return os.path.join(tempfile.gettempdir(), "kc_oracle_native_%s.so" % h.hexdigest()[:16])
+
+
+def build(force=False, native=False):
+    """Compile kc_oracle.c with gcc (-O3, OpenMP, no FMA contraction); with
+    native=True also -march=native, into a per-host file.  The flags leave the
+    arithmetic unchanged: no contraction, and no reassociation of sums (no
+    -ffast-math), so both builds give the same bits."""
+    path = _native_path() if native else _LIB_PATH
+    if not force and os.path.exists(path) and os.path.getmtime(path) >= os.path.getmtime(_SRC):
+        return path
+    tmp = path + ".tmp%d" % os.getpid()
+    cmd = ["gcc"] + FLAGS + (["-march=native"] if native else []) + ["-o", tmp, _SRC, "-lm"]
     subprocess.run(cmd, check=True)
-    os.replace(tmp, _LIB_PATH)
-    return _LIB_PATH
+    os.replace(tmp, path)
+    return path
+
+
+def use_native():
+    """Switch this process to the -march=native build (the CPU-baseline timing
+    leg); returns its gcc flags."""
+    global _lib
+    _lib = _bind(ctypes.CDLL(build(native=True)))
+    return " ".join(["gcc"] + FLAGS + ["-march=native"])
 
 
 def _load():
     global _lib
     if _lib is None:
-        build()
-        lib = ctypes.CDLL(_LIB_PATH)
-        dp = ctypes.POINTER(ctypes.c_double)
-        lib.oracle_step.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
-                                    ctypes.c_double, ctypes.c_double, ctypes.c_double,
-                                    ctypes.c_double, ctypes.c_int, dp, dp, dp, dp, dp]
-        lib.oracle_step.restype = None
-        lib.oracle_run.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
-                                   ctypes.c_double, ctypes.c_double, ctypes.c_double,
-                                   ctypes.c_double, ctypes.c_int, dp, dp, dp, ctypes.c_long]
-        lib.oracle_run.restype = ctypes.c_int
-        lib.oracle_run_rk2.argtypes = lib.oracle_run.argtypes
-        lib.oracle_run_rk2.restype = ctypes.c_int
-        u32p = ctypes.POINTER(ctypes.c_uint32)
-        lib.oracle_philox4x32_10.argtypes = [u32p, u32p, u32p]
-        lib.oracle_philox4x32_10.restype = None
-        lib.oracle_noise_delta.argtypes = [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int,
-                                           ctypes.c_int]
-        lib.oracle_noise_delta.restype = ctypes.c_double
-        lib.oracle_run_noise.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double,
-                                         ctypes.c_double, ctypes.c_double, ctypes.c_double,
-                                         ctypes.c_double, ctypes.c_double, ctypes.c_int, dp, dp,
-                                         ctypes.c_double, ctypes.c_double, ctypes.c_uint64,
-                                         ctypes.c_int64, ctypes.c_long, ctypes.c_int]
-        lib.oracle_run_noise.restype = ctypes.c_int
-        lib.oracle_diag.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, dp, dp,
-                                    ctypes.c_double, ctypes.c_double, ctypes.c_double,
-                                    dp, dp, dp, dp]
-        lib.oracle_diag.restype = None
-        lib.oracle_threads.argtypes = []
-        lib.oracle_threads.restype = ctypes.c_int
-        lib.oracle_set_threads.argtypes = [ctypes.c_int]
-        lib.oracle_set_threads.restype = None
-        _lib = lib
+        _lib = _bind(ctypes.CDLL(build()))
     return _lib
+
+
+def _bind(lib):
+    dp = ctypes.POINTER(ctypes.c_double)
+    lib.oracle_step.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                ctypes.c_double, ctypes.c_int, dp, dp, dp, dp, dp]
+    lib.oracle_step.restype = None
+    lib.oracle_run.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                               ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                               ctypes.c_double, ctypes.c_int, dp, dp, dp, ctypes.c_long]
+    lib.oracle_run.restype = ctypes.c_int
+    lib.oracle_run_rk2.argtypes = lib.oracle_run.argtypes
+    lib.oracle_run_rk2.restype = ctypes.c_int
+    u32p = ctypes.POINTER(ctypes.c_uint32)
+    lib.oracle_philox4x32_10.argtypes = [u32p, u32p, u32p]
+    lib.oracle_philox4x32_10.restype = None
+    lib.oracle_noise_delta.argtypes = [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int,
+                                       ctypes.c_int]
+    lib.oracle_noise_delta.restype = ctypes.c_double
+    lib.oracle_run_noise.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                     ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                     ctypes.c_double, ctypes.c_double, ctypes.c_int, dp, dp,
+                                     ctypes.c_double, ctypes.c_double, ctypes.c_uint64,
+                                     ctypes.c_int64, ctypes.c_long, ctypes.c_int]
+    lib.oracle_run_noise.restype = ctypes.c_int
+    lib.oracle_diag.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, dp, dp,
+                                ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                dp, dp, dp, dp]
+    lib.oracle_diag.restype = None
+    lib.oracle_threads.argtypes = []
+    lib.oracle_threads.restype = ctypes.c_int
+    lib.oracle_set_threads.argtypes = [ctypes.c_int]
+    lib.oracle_set_threads.restype = None
+    return lib
 
 
 def _f64(a):

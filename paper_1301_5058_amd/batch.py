@@ -90,16 +90,26 @@ class Batch:
                                         ctypes.c_void_p(n.ctypes.data), N.KC_MEM_HOST))
         return b, n
 
-    def fit_velocity(self, r_lo, r_hi, radius="envelope"):
+    def fit_velocity(self, r_lo, r_hi, radius="envelope", t_max=None):
+        """Device least-squares dR/dt over the samples with r_lo <= R <= r_hi
+        (and t <= t_max when given: kb_fit_velocity_until)."""
         lo = np.ascontiguousarray(np.broadcast_to(np.asarray(r_lo, np.float64), (self.count,)))
         hi = np.ascontiguousarray(np.broadcast_to(np.asarray(r_hi, np.float64), (self.count,)))
         v = np.empty(self.count, dtype=np.float64)
         npts = np.empty(self.count, dtype=np.int32)
         sel = 0 if radius == "envelope" else 1
-        self._chk(N.lib().kb_fit_velocity(self.h, sel, ctypes.c_void_p(lo.ctypes.data),
-                                          ctypes.c_void_p(hi.ctypes.data),
-                                          ctypes.c_void_p(v.ctypes.data),
-                                          ctypes.c_void_p(npts.ctypes.data)))
+        if t_max is None:
+            self._chk(N.lib().kb_fit_velocity(self.h, sel, ctypes.c_void_p(lo.ctypes.data),
+                                              ctypes.c_void_p(hi.ctypes.data),
+                                              ctypes.c_void_p(v.ctypes.data),
+                                              ctypes.c_void_p(npts.ctypes.data)))
+        else:
+            tm = np.ascontiguousarray(np.broadcast_to(np.asarray(t_max, np.float64), (self.count,)))
+            self._chk(N.lib().kb_fit_velocity_until(self.h, sel, ctypes.c_void_p(lo.ctypes.data),
+                                                    ctypes.c_void_p(hi.ctypes.data),
+                                                    ctypes.c_void_p(tm.ctypes.data),
+                                                    ctypes.c_void_p(v.ctypes.data),
+                                                    ctypes.c_void_p(npts.ctypes.data)))
         return v, npts
 
     def set_tuning(self, tsteps=0, rows=None, prefetch=0, persistent=-1):

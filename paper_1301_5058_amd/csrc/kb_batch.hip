@@ -253,18 +253,19 @@ __global__ void series_zero(double *series, size_t n)
 }
 
 // Least-squares slope per instance, one wavefront each, fixed order; `col`
-// selects the radius (3 envelope, 4 area) of the 5-double samples.
+// selects the radius (3 envelope, 4 area) of the 5-double samples; win holds
+// (lo, hi, t_max) per instance: samples with lo <= R <= hi and t <= t_max.
 __global__ __launch_bounds__(64) void kb_fit(const double *series, int cap, int nsamp, int col,
                                              const double *win, double *v, int *npts)
 {
     const int k = blockIdx.x;
     const int lane = threadIdx.x;
-    const double lo = win[2 * k], hi = win[2 * k + 1];
+    const double lo = win[3 * k], hi = win[3 * k + 1], tmax = win[3 * k + 2];
     const double *S = series + (size_t)k * cap * 5;
     double c = 0.0, st = 0.0, sr = 0.0;
     for (int s = lane; s < nsamp; s += 64) {
         const double R = S[5 * s + col];
-        if (R >= lo && R <= hi) {
+        if (R >= lo && R <= hi && S[5 * s + 0] <= tmax) {
             c += 1.0;
             st += S[5 * s + 0];
             sr += R;
@@ -277,7 +278,7 @@ __global__ __launch_bounds__(64) void kb_fit(const double *series, int cap, int 
     double sxy = 0.0, sxx = 0.0;
     for (int s = lane; s < nsamp; s += 64) {
         const double R = S[5 * s + col];
-        if (R >= lo && R <= hi) {
+        if (R >= lo && R <= hi && S[5 * s + 0] <= tmax) {
             const double dt = S[5 * s + 0] - tm;
             sxy += dt * (R - rm);
             sxx += dt * dt;
@@ -659,7 +660,7 @@ int kb_create(int32_t count, const kb_instance *inst, int32_t chi_law, int32_t m
     if (e == hipSuccess)
         e = hipMalloc((void **)&b->dseries, (size_t)count * max_samples * 5 * sizeof(double));
     if (e == hipSuccess)
-        e = hipMalloc((void **)&b->dwin, (size_t)count * 2 * sizeof(double));
+        e = hipMalloc((void **)&b->dwin, (size_t)count * 3 * sizeof(double));
     if (e == hipSuccess)
         e = hipMalloc((void **)&b->dv, (size_t)count * sizeof(double));
     if (e == hipSuccess)
@@ -943,6 +944,12 @@ int kb_get_fields(kb_batch *b, int32_t k, float *bo, float *no, int mem)
 int kb_fit_velocity(kb_batch *b, int32_t radius, const double *r_lo, const double *r_hi,
                     double *v, int32_t *npoints)
 {
+    return kb_fit_velocity_until(b, radius, r_lo, r_hi, nullptr, v, npoints);
+}
+
+int kb_fit_velocity_until(kb_batch *b, int32_t radius, const double *r_lo, const double *r_hi,
+                          const double *t_max, double *v, int32_t *npoints)
+{
     if (!b)
         return KC_EINVAL;
     b->err.clear();
@@ -950,13 +957,18 @@ int kb_fit_velocity(kb_batch *b, int32_t radius, const double *r_lo, const doubl
         return bfail(b, KC_EINVAL, "null pointer");
     if (radius != KB_RADIUS_ENVELOPE && radius != KB_RADIUS_AREA)
         return bfail(b, KC_EINVAL, "bad radius selector %d", radius);
+    if (t_max)
+        for (int k = 0; k < b->count; ++k)
+            if (isnan(t_max[k]))
+                return bfail(b, KC_EINVAL, "t_max[%d] is NaN", k);
     if (ensure_pinned(b, 3 * (size_t)b->count) != KC_OK)
         return KC_ENOMEM;
     for (int k = 0; k < b->count; ++k) {
-        b->hpin[2 * k] = r_lo[k];
-        b->hpin[2 * k + 1] = r_hi[k];
+        b->hpin[3 * k] = r_lo[k];
+        b->hpin[3 * k + 1] = r_hi[k];
+        b->hpin[3 * k + 2] = t_max ? t_max[k] : (double)INFINITY;
     }
-    KB_HIP(b, hipMemcpyAsync(b->dwin, b->hpin, 2 * b->count * sizeof(double),
+    KB_HIP(b, hipMemcpyAsync(b->dwin, b->hpin, 3 * b->count * sizeof(double),
                              hipMemcpyHostToDevice, b->stream));
     hipLaunchKernelGGL(kc::kb_fit, dim3(b->count), dim3(64), 0, b->stream, b->dseries, b->cap,
                        b->nsamp, radius == KB_RADIUS_AREA ? 4 : 3, b->dwin, b->dv, b->dnpts);

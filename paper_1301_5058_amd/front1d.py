@@ -6,7 +6,9 @@ instances in one batch (kb_* calls), the front position sampled on the device
 as the envelope radius about x = 0 (centre at cell index -1/2, threshold
 b_thr = min(0.5, n0 / 2): the paper's "vicinity of 0.5", below the plateau n0
 for poor nutrient), and its velocity fitted on the device over the window of
-front positions.  The velocities are compared with the
+front positions up to the front's own end time (its first sample past the
+window, or the time a quarter-c-bar front needs to cross it).  The velocities
+are compared with the
 closed-form bound c-bar(n0, chi0) of Sec. 4.1 (ks_cbar) and with the threshold
 speed c* of the scalar front equation (ks_cstar); the speeds over the
 two halves of the window tell a steady front from one that still changes
@@ -77,8 +79,15 @@ def run_front1d(cells=None, n0s=None, chis=None, steps=None):
     pts = [(d["n0"], d["chi"]) for d in descs]
     cbar, cstar = speed_bounds(pts, c["sigma0"], threshold=True)
     lo, hi = c["window"]
+    # A front's run ends at its first sample past hi + 1/2, or at the time a
+    # front moving at a quarter of c-bar needs to cross from the inoculum's
+    # edge to hi (a slow front that stalls ends there); its speed is fitted
+    # over the samples up to that end.
+    t_cap = 4.0 * (hi - c["cut"] * c["r0"]) / np.asarray(cbar, dtype=np.float64)
     if steps is None:
         steps = steps_needed(descs, cbar, hi)
+        longest = max(tc / d["dt"] for tc, d in zip(t_cap, descs))
+        steps = max(steps, int(math.ceil(longest / SAMPLE_EVERY)) * SAMPLE_EVERY)
     B = Batch(descs, chi_law="constant", max_samples=steps // SAMPLE_EVERY + 1)
     try:
         for k, (b, n, s) in enumerate(fields):
@@ -89,19 +98,24 @@ def run_front1d(cells=None, n0s=None, chis=None, steps=None):
         t0 = time.perf_counter()
         e0.record(st)
         B.run(steps, SAMPLE_EVERY)
-        v, npts = B.fit_velocity(lo, hi, radius="envelope")
+        series = B.series()
+        t_end = np.empty(len(descs))
+        for k in range(len(descs)):
+            ts, rs = series[k, :, 0], series[k, :, 3]
+            stop = np.nonzero((rs >= hi + 0.5) | (ts >= t_cap[k]))[0]
+            t_end[k] = ts[stop[0]] if len(stop) else ts[-1]
+        v, npts = B.fit_velocity(lo, hi, radius="envelope", t_max=t_end)
         mid = 0.5 * (lo + hi)
-        v1, _ = B.fit_velocity(lo, mid, radius="envelope")
-        v2, _ = B.fit_velocity(mid, hi, radius="envelope")
+        v1, _ = B.fit_velocity(lo, mid, radius="envelope", t_max=t_end)
+        v2, _ = B.fit_velocity(mid, hi, radius="envelope", t_max=t_end)
         e1.record(st)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
-        series = B.series()
     finally:
         B.close()
     # a front is steady when its speeds over the two halves of the window agree
     steady = np.isfinite(v1) & np.isfinite(v2) & (np.abs(v1 - v2) <= 0.1 * np.abs(v))
     return dict(points=pts, velocity=v, samples=npts, cbar=cbar, cstar=cstar, steps=steps,
-                velocity_halves=(v1, v2), steady=steady,
+                velocity_halves=(v1, v2), steady=steady, t_end=t_end,
                 dt=[d["dt"] for d in descs], cells=descs[0]["nx"], window=(lo, hi),
                 gpu_s=e0.elapsed_time(e1) / 1e3, wall_s=wall, series=series)

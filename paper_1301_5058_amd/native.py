@@ -82,6 +82,8 @@ _SIGS = {
     "kb_series": (c_int32, [c_void_p, c_void_p, ctypes.POINTER(c_int32), c_int32]),
     "kb_get_fields": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_int32]),
     "kb_fit_velocity": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "kb_fit_velocity_until": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p,
+                                        c_void_p]),
     "kb_set_tuning": (c_int32, [c_void_p, c_int32, c_void_p, c_int32, c_int32]),
     "kb_get_tuning": (c_int32, [c_void_p, ctypes.POINTER(c_int32), c_void_p,
                                 ctypes.POINTER(c_int32), ctypes.POINTER(c_int32)]),

@@ -1,9 +1,11 @@
 """Grid-resolution study of the one-dimensional front experiment (Sec. 4.2,
 system velo-system-1d) with the FP64 oracle only.
 
-    python tests/golden/front1d_resolution.py [--jobs 5] [--cells 400,800,1600,3200]
+    python tests/golden/front1d_resolution.py [--jobs 5] [--cells 400,800,1600,3200] [--points hard|all]
 
-For each (n0, chi0) below and each grid of `cells` cells on [0, 20] the oracle
+For each (n0, chi0) below (`hard`: the six points whose fronts are fastest,
+burst or stall; `all`: the experiment's 30) and each grid of `cells` cells on
+[0, 20] the oracle
 runs the experiment's set-up (constant sensitivity, sigma = 1, the cut
 inoculum 0.71 exp(-x^2 / 6.25), forward Euler at the experiment's time step
 0.2 h^2 / max(D_n, sigma0 n0 (n0 + b_M)(1 + chi0 n0)), which scales with h^2)
@@ -15,9 +17,11 @@ moving at a quarter of the bound c-bar of Sec. 4.1 needs to cross [7.5, 17].
 Written out per run: the time step, the final time, the final front position,
 the least-squares speed over the window x in [9, 17] and over its two halves
 (NaN when fewer than three samples fall in it), and the speed over the last
-quarter of the run.  The table is written to front1d_resolution.txt beside
-this script; the GPU tests compare the library's 400-cell runs with its
-400-cell rows.
+quarter of the run.  Rows are merged into front1d_resolution.txt beside this
+script (a new row replaces the one with the same n0, chi0 and cells); the GPU
+tests compare the library's 400-cell runs with the rows of the hard points,
+and the benchmark flags a front as resolved when its 400-cell speed is within
+1 % of the speed on the finest grid of the table.
 """
 import argparse
 import math
@@ -34,6 +38,8 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 POINTS = [(4.0, 10.0), (4.0, 5.0), (3.0, 10.0), (2.0, 2.5), (0.71, 0.0), (0.35, 0.0)]
+ALL_POINTS = [(n0, chi) for n0 in (0.35, 0.71, 1.07, 2.0, 3.0, 4.0)
+              for chi in (0.0, 1.0, 2.5, 5.0, 10.0)]
 CELLS = (400, 800, 1600, 3200)
 LENGTH, B_MAX, R0, CUT, SIGMA0 = 20.0, 0.71, 2.5, 3.0, 1.0
 WINDOW = (9.0, 17.0)
@@ -100,9 +106,11 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--jobs", type=int, default=5)
     ap.add_argument("--cells", default=",".join(str(c) for c in CELLS))
+    ap.add_argument("--points", choices=("hard", "all"), default="hard")
     a = ap.parse_args()
     cells = [int(c) for c in a.cells.split(",")]
-    jobs = [(n0, chi, c) for c in cells for (n0, chi) in POINTS]
+    points = POINTS if a.points == "hard" else ALL_POINTS
+    jobs = [(n0, chi, c) for c in cells for (n0, chi) in points]
     # longest runs first
     jobs.sort(key=lambda j: -j[2])
     rows = []
@@ -113,8 +121,19 @@ def main():
                                                      r["v2"], r["v"] / r["cbar"], r["r_end"],
                                                      r["t_end"], r["seconds"]), flush=True)
             rows.append(r)
-    rows.sort(key=lambda r: (-r["n0"], -r["chi"], r["cells"]))
     out = os.path.join(HERE, "front1d_resolution.txt")
+    cols = ("n0", "chi", "cells", "dt", "steps", "t_end", "r_end", "v", "v1", "v2", "v_last", "cbar")
+    new = {(round(r["n0"], 2), round(r["chi"], 1), r["cells"]) for r in rows}
+    if os.path.exists(out):
+        for line in open(out):
+            if line.startswith("#") or not line.strip():
+                continue
+            f = line.split()
+            old = dict(zip(cols, [float(x) for x in f]))
+            old["cells"], old["steps"] = int(f[2]), int(f[4])
+            if (round(old["n0"], 2), round(old["chi"], 1), old["cells"]) not in new:
+                rows.append(old)
+    rows.sort(key=lambda r: (-r["n0"], -r["chi"], r["cells"]))
     with open(out, "w") as f:
         f.write("# Resolution study of the 1-D front experiment of Sec. 4.2 (system velo-system-1d),\n"
                 "# FP64 oracle only; written by tests/golden/front1d_resolution.py.\n"

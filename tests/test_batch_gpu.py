@@ -125,6 +125,19 @@ def test_velocity_fit_equals_oracle_fit_of_same_series():
         assert v[1] > v[0] > 0
     v2, n2 = B.fit_velocity(1e6, 2e6)
     assert np.all(np.isnan(v2)) and np.all(n2 == 0)
+    # kb_fit_velocity_until: only the samples up to each instance's t_max
+    t_max = np.array([ser[0, 17, 0], ser[1, 24, 0]])
+    v3, n3 = B.fit_velocity(lo, hi, t_max=t_max)
+    for k in range(2):
+        sel = ser[k, :, 0] <= t_max[k]
+        vo, ko = oracle.fit_velocity(ser[k, sel, 0], ser[k, sel, 3], lo[k], hi[k])
+        assert n3[k] == ko and v3[k] == pytest.approx(vo, rel=1e-12)
+    v4, _ = B.fit_velocity(lo, hi, t_max=np.inf)
+    assert np.array_equal(v4, B.fit_velocity(lo, hi)[0])
+    from paper_1301_5058_amd import native as N
+    with pytest.raises(N.KcError) as e:
+        B.fit_velocity(lo, hi, t_max=np.nan)
+    assert e.value.code == N.KC_EINVAL
     B.close()
 
 

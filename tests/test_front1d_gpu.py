@@ -81,7 +81,9 @@ def test_front1d_chemotaxis_speeds_the_front_up():
     # slow them (Sec. 4.2, Proposition 1) and they move at a speed close to the
     # bound c-bar.  Slow fronts at small n0 deplete the nutrient ahead of them
     # (it diffuses with D_n = 1 into the colony) and keep decelerating, and
-    # chi0 n0 = 40 is not resolved on 400 cells; those are reported only.
+    # strong chemotaxis sends a burst ahead that still decays in the window;
+    # those speeds are converged (the oracle's resolution study) but not
+    # steady, and are checked against the study only.
     r = front1d.run_front1d()
     pts, v, cb, st = np.array(r["points"]), r["velocity"], r["cbar"], r["steady"]
     cs = r["cstar"]
@@ -121,13 +123,17 @@ def _resolution_table():
 
 
 def test_front1d_speeds_match_the_oracle_resolution_study():
-    # The batch's 400-cell fronts at the points of the oracle's resolution study
-    # (tests/golden/front1d_resolution.txt, written by the FP64 oracle alone),
-    # fitted over the same samples (radius window [9, 17], up to the study's
-    # end time): within 1 % of its 400-cell speeds (the FP32 / FP64 bar of the
-    # series test; the FP32 rounding bias reaches 0.85 % at n0 = 4, chi0 = 10),
-    # and within the spread the study shows between 400 and 3200 cells, plus
-    # that bar, of the converged (3200-cell) speeds.
+    # The experiment's 30 fronts on 400 cells against the oracle's resolution
+    # study (tests/golden/front1d_resolution.txt, written by the FP64 oracle
+    # alone; every point at 400 and 800 cells, six up to 3200).  The library's
+    # speed (fitted on the device up to each front's end time, the study's
+    # protocol) is within 1 % of the study's 400-cell speed (the FP32 / FP64
+    # bar of the series test; FP32 rounding biases the n0 = 4, chi0 = 10 front
+    # by 0.85 %), and within the study's spread between 400 cells and its
+    # finest grid, plus that bar, of the finest grid's speed.  Each run ends
+    # where the study's does, to within one sample plus the time the front
+    # needs to cover the series test's position bar (one cell plus 1 % of the
+    # end position).
     tab = _resolution_table()
     pts = sorted({(k[0], k[1]) for k in tab}, reverse=True)
     n0s = sorted({p[0] for p in pts})
@@ -136,13 +142,23 @@ def test_front1d_speeds_match_the_oracle_resolution_study():
     index = {(round(p[0], 2), round(p[1], 1)): k for k, p in enumerate(r["points"])}
     lo, hi = workload.FRONT1D["window"]
     for (n0, chi) in pts:
+        k = index[(n0, chi)]
         row = tab[(n0, chi, 400)]
-        ser = r["series"][index[(n0, chi)]]
-        sel = ser[:, 0] <= row["t_end"] * (1 + 1e-9)
-        v, _ = oracle.fit_velocity(ser[sel, 0], ser[sel, 3], lo, hi)
-        ref400, ref3200 = row["v"], tab[(n0, chi, 3200)]["v"]
-        spread = abs(ref400 - ref3200) / ref3200
-        print("n0 %.2f chi0 %4.1f: GPU %.6g, oracle 400 cells %.6g, 3200 cells %.6g (c-bar %.4g)"
-              % (n0, chi, v, ref400, ref3200, row["cbar"]))
+        finest = max(c for (a, b, c) in tab if (a, b) == (n0, chi))
+        ref400, ref_f = row["v"], tab[(n0, chi, finest)]["v"]
+        spread = abs(ref400 - ref_f) / ref_f
+        v = r["velocity"][k]
+        # the same fit by the oracle's routine over the same samples
+        ser = r["series"][k]
+        sel = ser[:, 0] <= r["t_end"][k] * (1 + 1e-12)
+        ov, _ = oracle.fit_velocity(ser[sel, 0], ser[sel, 3], lo, hi)
+        every_dt = front1d.SAMPLE_EVERY * row["dt"]
+        print("n0 %.2f chi0 %4.1f: GPU %.6g, oracle 400 cells %.6g, %d cells %.6g (c-bar %.4g), "
+              "end %.6g vs %.6g" % (n0, chi, v, ref400, finest, ref_f, row["cbar"], r["t_end"][k],
+                                   row["t_end"]))
+        h = workload.FRONT1D["length"] / 400
+        assert abs(r["t_end"][k] - row["t_end"]) <= every_dt * (1 + 1e-6) + \
+            (h + 0.01 * (hi + 0.5)) / ref400
+        assert abs(v - ov) <= 1e-9 * abs(ov)
         assert abs(v - ref400) <= 0.01 * ref400
-        assert abs(v - ref3200) <= spread * ref3200 + 0.01 * ref400
+        assert abs(v - ref_f) <= spread * ref_f + 0.01 * ref400

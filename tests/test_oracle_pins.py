@@ -568,3 +568,22 @@ def test_noise_runs_reduce_to_the_static_field_and_keep_the_invariants():
     assert np.array_equal(a1, p1) and np.array_equal(a2, p2)
     o1, _ = oracle.run_noise(b0, n0, 1.0, dt, 40, 1.0, 0.5, 100, chi=0.5)
     assert not np.array_equal(a1, o1)
+
+
+def test_native_build_gives_the_same_bits():
+    # The CPU-baseline leg times the oracle built with -march=native; the flags
+    # keep FMA contraction and reassociation off, so it computes the same bits.
+    rng = np.random.default_rng(11)
+    b, n = rng.random((30, 41)), rng.random((30, 41))
+    s = 1.0 + 0.5 * rng.random((30, 41))
+    ref = oracle.run(b, n, s, 1.0, 0.02, 25, chi=1.5)
+    ref_d = oracle.diag(ref[0], ref[1], 1.0, 0.5)
+    saved = oracle._lib
+    try:
+        oracle.use_native()
+        got = oracle.run(b, n, s, 1.0, 0.02, 25, chi=1.5)
+        got_d = oracle.diag(got[0], got[1], 1.0, 0.5)
+    finally:
+        oracle._lib = saved
+    assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1])
+    assert tuple(got_d) == tuple(ref_d)

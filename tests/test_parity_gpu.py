@@ -251,6 +251,10 @@ def test_full_size_sampled_cells_match_oracle(cfg, launches):
     dt = workload.config_dt(b, n, s)
     S = Solver(nx, ny, dt=dt, chi=cfg["chi"], b_thr=0.5 * cfg["n0"])
     S.set_fields(torch.from_numpy(b).cuda(), torch.from_numpy(n).cuda(), torch.from_numpy(s).cuda())
+    # the launch configuration the benchmark times (shipped tuning database)
+    tuning = _shipped_tuning("|%dx%d|fp32|receptor" % (nx, ny), exact=True)
+    assert tuning is not None
+    S.set_tuning(*tuning)
     T = S.tuning()[0]
     steps = T * launches
     # make the colony non-trivial first, in the same configuration
@@ -281,7 +285,7 @@ def _shipped_tuning(key_part, exact=False):
     for line in open(path):
         e = json.loads(line)
         if (e["key"].endswith(key_part) if exact else key_part in e["key"]):
-            return e["tsteps"], e["rows"], e["prefetch"]
+            return e["tsteps"], e["rows"], e["prefetch"], e.get("waves", 1)
     return None
 
 
