@@ -131,7 +131,7 @@ def run_case(sigma0, n0, chi, times, dt_paper, cells=2048, length=680.0, seed=1,
     try:
         S.set_fields(torch.from_numpy(b).cuda(), torch.from_numpy(n).cuda())
         S.autotune(effort=0, use_cache=True)
-        tuning = S.tuning()
+        tuning = S.tuning() + (S.strip_waves(),)
         chunk = max(1, int(chunk_cell_steps / (cells * cells)))
         recs, keep = [], []
         done, gpu_ms = 0, 0.0

@@ -2,7 +2,7 @@
 
     python -m paper_1301_5058_amd.run [--nx 4096] [--ny NX] [--precision fp32|fp64]
         [--integrator euler|rk2] [--noise] [--chi 1.0] [--n0 0.5] [--amp 0.5]
-        [--steps 400] [--warmup 100] [--tuning T,ROWS,PF] [--paper-set NAME]
+        [--steps 400] [--warmup 100] [--tuning T,ROWS,PF[,WAVES]] [--paper-set NAME]
         [--copy-ref-mib M]
 
 The workload is the seeded synthetic one of the library's benchmarks (uniform
@@ -84,11 +84,12 @@ def main(argv=None):
         integrator = a.integrator
     S.set_fields(*(torch.from_numpy(x).cuda() for x in fields))
     if a.tuning:
-        t, r, p = (int(v) for v in a.tuning.split(","))
-        S.set_tuning(t, r, p)
+        vals = [int(v) for v in a.tuning.split(",")]
+        S.set_tuning(*vals)
     else:
         S.autotune(effort=0, use_cache=True)
     T, rows, pf = S.tuning()
+    waves = S.strip_waves()
     S.step(a.warmup)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -101,6 +102,7 @@ def main(argv=None):
     S.close()
     out = {"nx": nx, "ny": ny, "precision": a.precision, "integrator": integrator,
            "noise": noise is not None, "steps": a.steps, "tsteps": T, "rows": rows, "prefetch": pf,
+           "waves_per_strip": waves,
            "ms": round(ms, 4), "gcell_steps_s": round(nx * ny * a.steps / (ms * 1e-3) / 1e9, 2),
            "mass": m, "nutrient": nu, "envelope_radius": r}
     print(json.dumps(out), flush=True)
