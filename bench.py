@@ -65,7 +65,9 @@ FLOPS_PER_CELL_UPDATE = 55
 METRIC = "GCell-updates/s & % HBM peak (4096^2 FP32); velocity-map pts/s at <=2% err"
 STEP_SOURCES = ("paper_1301_5058_amd/csrc/kc_step.hip", "paper_1301_5058_amd/csrc/kc_step_kernels.h",
                 "paper_1301_5058_amd/csrc/kc_stream_f32_euler.hip",
-                "paper_1301_5058_amd/csrc/kc_stream.h", "paper_1301_5058_amd/csrc/kc_device.h")
+                "paper_1301_5058_amd/csrc/kc_stream_f32_euler4.hip",
+                "paper_1301_5058_amd/csrc/kc_stream.h", "paper_1301_5058_amd/csrc/kc_device.h",
+                "paper_1301_5058_amd/build.py")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_stream_4096_fp32_traffic.txt")
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "step_stream_4096_fp32_counters.txt")
 # shipped autotune database (written by paper_1301_5058_amd/tune_db.py on an MI355X);

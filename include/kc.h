@@ -222,8 +222,12 @@ int kc_get_strip_waves(const kc_ctx *ctx, int32_t *waves);
 
 /* Pick the fused-kernel configuration (as kc_set_tuning and
  * kc_set_strip_waves) by timing candidate launches on the context's own
- * fields: each launch reads the current level and writes the scratch level,
- * so the state is unchanged.  effort 0 tries 4 depths x 4 strip heights with
+ * fields: a candidate's first launch reads the current level and writes the
+ * scratch level, and its timed launches alternate between the scratch level
+ * and a temporary one (allocated for the call and freed before it returns;
+ * when it cannot be allocated they repeat the first launch), as a run
+ * alternates between its two levels; the current level is never written, so
+ * the state is unchanged.  effort 0 tries 4 depths x 4 strip heights with
  * prefetch 4, effort 1 6 depths x 10 heights x prefetch 2 and 4; each with one
  * wavefront per strip and, where the depth splits, two; both add, per depth,
  * prefetch and wavefront count, the strip heights that fill 1..8 whole rounds

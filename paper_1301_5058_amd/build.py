@@ -42,9 +42,15 @@ def sources():
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hip"))
 
 
+# Per-unit flags: the four-level FP32 Euler kernels use the latency-first
+# (max-ILP) machine scheduler, which is faster for them and slower elsewhere.
+UNIT_FLAGS = {"kc_stream_f32_euler4.hip": ["-mllvm", "-amdgpu-sched-strategy=max-ilp"]}
+
+
 def _compile(src, extra):
     obj = os.path.join(OBJDIR, os.path.basename(src) + ".o")
-    cmd = [hipcc()] + COMMON + extra + ["-I", INCLUDE, "-I", CSRC, "-c", src, "-o", obj]
+    cmd = [hipcc()] + COMMON + UNIT_FLAGS.get(os.path.basename(src), []) + extra + \
+        ["-I", INCLUDE, "-I", CSRC, "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("hipcc failed for %s:\n%s\n%s" % (src, " ".join(cmd), r.stderr))

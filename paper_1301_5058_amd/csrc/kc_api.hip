@@ -397,6 +397,23 @@ template <typename R> int autotune_impl(kc_ctx *c, int effort, double *best_out)
     kc::tuning_candidates(effort, c->p.precision, c->p.chi_law, c->p.integrator, noise, c->nx,
                           c->ny, cand, &n, 512);
     const double cells = (double)c->nx * c->ny;
+    // a spare level, so that the timed launches alternate between two levels
+    // like a run's (freed below; without it the launches repeat in place)
+    const size_t level = (size_t)c->pitch * c->ny * sizeof(R);
+    R *tmp = nullptr;
+    if (hipMalloc((void **)&tmp, 2 * level) != hipSuccess) {
+        (void)hipGetLastError();
+        tmp = nullptr;
+    }
+    R *tmp_b = tmp, *tmp_n = tmp ? tmp + level / sizeof(R) : nullptr;
+    struct Free {
+        R *p;
+        ~Free()
+        {
+            if (p)
+                (void)hipFree(p);
+        }
+    } free_tmp{tmp};
     // pass 1: every candidate once; pass 2: the six fastest again, twice each
     // with longer runs, keeping each one's best (single timings are noisy)
     std::vector<std::pair<double, int>> order;
@@ -407,7 +424,7 @@ template <typename R> int autotune_impl(kc_ctx *c, int effort, double *best_out)
         double ms = 0;
         hipError_t e =
             kc::time_stream<R>(f, k, c->p.chi_law, c->p.integrator, cand[i], c->stream, reps, &ms,
-                               zp);
+                               zp, tmp_b, tmp_n);
         if (e != hipSuccess)
             return hipfail(c, e, "autotune launch");
         order.push_back(std::make_pair(ms / cand[i].tsteps, i));
@@ -424,7 +441,7 @@ template <typename R> int autotune_impl(kc_ctx *c, int effort, double *best_out)
             double ms = 0;
             hipError_t e =
                 kc::time_stream<R>(f, k, c->p.chi_law, c->p.integrator, t, c->stream, reps, &ms,
-                                   zp);
+                                   zp, tmp_b, tmp_n);
             if (e != hipSuccess)
                 return hipfail(c, e, "autotune launch");
             if (ms / t.tsteps < best) {

@@ -86,12 +86,17 @@ hipError_t launch_ref(const Fields<R> &f, const Coef<R> &c, int chi_law, hipStre
                       const Noise<R> *z = nullptr);
 
 // Average duration (ms) of one fused launch with tuning t, from `reps` launches
-// after one warm-up launch, timed with HIP events on stream s.  The launch
-// reads f's input level and writes its output level; nothing else changes.
+// after one warm-up launch, timed with HIP events on stream s.  The warm-up
+// reads f's input level and writes its output level.  With tmp_b, tmp_n (a
+// spare level of f's size) the timed launches then alternate between f's
+// output level and the spare one, as a run's launches alternate between its
+// two levels (the same working set; reading one level again and again would
+// keep it in the 256 MB last-level cache and flatter the timing); without,
+// they repeat the warm-up.  f's input level is never written.
 template <typename R>
 hipError_t time_stream(const Fields<R> &f, const Coef<R> &c, int chi_law, int integrator,
                        const Tuning &t, hipStream_t s, int reps, double *ms,
-                       const Noise<R> *z = nullptr);
+                       const Noise<R> *z = nullptr, R *tmp_b = nullptr, R *tmp_n = nullptr);
 
 // Wavefronts of the fused kernel (precision, law, integrator, depth, prefetch)
 // that the device holds at once: blocks per compute unit x 4 x compute units

@@ -207,8 +207,21 @@ hipError_t launch_ref(const Fields<R> &f, const Coef<R> &c, int chi_law, hipStre
 
 template <typename R>
 hipError_t time_stream(const Fields<R> &f, const Coef<R> &c, int chi_law, int integrator,
-                       const Tuning &t, hipStream_t s, int reps, double *ms, const Noise<R> *z)
+                       const Tuning &t, hipStream_t s, int reps, double *ms, const Noise<R> *z,
+                       R *tmp_b, R *tmp_n)
 {
+    // timed launches: f's output level <-> (tmp_b, tmp_n), or f itself again
+    Fields<R> fa = f, fb = f;
+    if (tmp_b && tmp_n) {
+        fa.b_in = f.b_out;
+        fa.n_in = f.n_out;
+        fa.b_out = tmp_b;
+        fa.n_out = tmp_n;
+        fb.b_in = tmp_b;
+        fb.n_in = tmp_n;
+        fb.b_out = f.b_out;
+        fb.n_out = f.n_out;
+    }
     hipEvent_t e0, e1;
     hipError_t e = hipEventCreate(&e0);
     if (e != hipSuccess)
@@ -222,7 +235,7 @@ hipError_t time_stream(const Fields<R> &f, const Coef<R> &c, int chi_law, int in
     if (e == hipSuccess)
         e = hipEventRecord(e0, s);
     for (int i = 0; i < reps && e == hipSuccess; ++i)
-        e = launch_stream<R>(f, c, chi_law, integrator, t, s, z);
+        e = launch_stream<R>(i % 2 ? fb : fa, c, chi_law, integrator, t, s, z);
     if (e == hipSuccess)
         e = hipEventRecord(e1, s);
     if (e == hipSuccess)
@@ -321,10 +334,10 @@ void tuning_candidates(int effort, int precision, int chi_law, int integrator, b
 
 template hipError_t time_stream<float>(const Fields<float> &, const Coef<float> &, int, int,
                                        const Tuning &, hipStream_t, int, double *,
-                                       const Noise<float> *);
+                                       const Noise<float> *, float *, float *);
 template hipError_t time_stream<double>(const Fields<double> &, const Coef<double> &, int, int,
                                         const Tuning &, hipStream_t, int, double *,
-                                        const Noise<double> *);
+                                        const Noise<double> *, double *, double *);
 template hipError_t launch_stream<float>(const Fields<float> &, const Coef<float> &, int, int,
                                          const Tuning &, hipStream_t, const Noise<float> *,
                                          const DiagReq *);

@@ -173,36 +173,55 @@ const void *pick_kernel(int pf, int waves)
                    : reinterpret_cast<const void *>(&step_stream<R, T, LAW, 2, RK, NOISE>);
 }
 
-template <typename R, int LAW, bool RK, bool NOISE>
+// pick_kernel for the level counts a translation unit instantiates: all of them
+// (ONLY = 0) or only ONLY, and never EXCLUDE (a kernel is compiled in exactly
+// one translation unit).
+template <typename R, int T, int LAW, bool RK, bool NOISE, int EXCLUDE, int ONLY>
+const void *pick_kernel_in_unit(int pf, int waves)
+{
+    if constexpr ((ONLY == 0 || ONLY == T) && EXCLUDE != T)
+        return pick_kernel<R, T, LAW, RK, NOISE>(pf, waves);
+    else
+        return nullptr;
+}
+
+template <typename R, int LAW, bool RK, bool NOISE, int EXCLUDE, int ONLY>
 const void *pick_levels(int levels, int pf, int waves)
 {
     if constexpr (RK) {
         switch (levels) {
-        case 2: return pick_kernel<R, 2, LAW, RK, NOISE>(pf, waves);
-        case 4: return pick_kernel<R, 4, LAW, RK, NOISE>(pf, waves);
-        case 6: return pick_kernel<R, 6, LAW, RK, NOISE>(pf, waves);
+        case 2: return pick_kernel_in_unit<R, 2, LAW, RK, NOISE, EXCLUDE, ONLY>(pf, waves);
+        case 4: return pick_kernel_in_unit<R, 4, LAW, RK, NOISE, EXCLUDE, ONLY>(pf, waves);
+        case 6: return pick_kernel_in_unit<R, 6, LAW, RK, NOISE, EXCLUDE, ONLY>(pf, waves);
         default: return nullptr;
         }
     } else {
         switch (levels) {
-        case 1: return pick_kernel<R, 1, LAW, RK, NOISE>(pf, waves);
-        case 2: return pick_kernel<R, 2, LAW, RK, NOISE>(pf, waves);
-        case 3: return pick_kernel<R, 3, LAW, RK, NOISE>(pf, waves);
-        case 4: return pick_kernel<R, 4, LAW, RK, NOISE>(pf, waves);
-        case 6: return pick_kernel<R, 6, LAW, RK, NOISE>(pf, waves);
-        case 8: return pick_kernel<R, 8, LAW, RK, NOISE>(pf, waves);
+        case 1: return pick_kernel_in_unit<R, 1, LAW, RK, NOISE, EXCLUDE, ONLY>(pf, waves);
+        case 2: return pick_kernel_in_unit<R, 2, LAW, RK, NOISE, EXCLUDE, ONLY>(pf, waves);
+        case 3: return pick_kernel_in_unit<R, 3, LAW, RK, NOISE, EXCLUDE, ONLY>(pf, waves);
+        case 4: return pick_kernel_in_unit<R, 4, LAW, RK, NOISE, EXCLUDE, ONLY>(pf, waves);
+        case 6: return pick_kernel_in_unit<R, 6, LAW, RK, NOISE, EXCLUDE, ONLY>(pf, waves);
+        case 8: return pick_kernel_in_unit<R, 8, LAW, RK, NOISE, EXCLUDE, ONLY>(pf, waves);
         default: return nullptr;
         }
     }
 }
 
-template <typename R, bool RK, bool NOISE>
+template <typename R, bool RK, bool NOISE, int EXCLUDE = 0, int ONLY = 0>
 const void *stream_kernel_table(int chi_law, int levels, int pf, int waves)
 {
     if ((pf != 2 && pf != 4) || (waves != 1 && waves != 2))
         return nullptr;
-    return chi_law == 0 ? pick_levels<R, 0, RK, NOISE>(levels, pf, waves)
-                        : pick_levels<R, 1, RK, NOISE>(levels, pf, waves);
+    return chi_law == 0 ? pick_levels<R, 0, RK, NOISE, EXCLUDE, ONLY>(levels, pf, waves)
+                        : pick_levels<R, 1, RK, NOISE, EXCLUDE, ONLY>(levels, pf, waves);
 }
+
+// The four-level FP32 forward-Euler kernels (the benchmark's), defined in
+// kc_stream_f32_euler4.hip, which is compiled with the latency-first
+// (max-ILP) machine scheduler: at their register budgets it interleaves
+// independent rows and cells more and runs them 2-3 % faster, while it slows
+// the deeper and the noise kernels, which stay with the default scheduler.
+const void *stream_kernel_f32_euler4(int chi_law, int pf, int waves);
 
 } // namespace kc

@@ -8,7 +8,9 @@ namespace kc {
 template <>
 const void *stream_kernel_for<float, false, false>(int chi_law, int levels, int pf, int waves)
 {
-    return stream_kernel_table<float, false, false>(chi_law, levels, pf, waves);
+    if (levels == 4)
+        return stream_kernel_f32_euler4(chi_law, pf, waves);
+    return stream_kernel_table<float, false, false, 4, 0>(chi_law, levels, pf, waves);
 }
 
 } // namespace kc
