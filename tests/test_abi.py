@@ -49,6 +49,9 @@ def test_strerror_and_null_context():
     assert L.kc_diagnostics(None, None, None, None) == N.KC_EINVAL
     assert L.kc_get_fields(None, None, None, 0) == N.KC_EINVAL
     assert L.kc_set_tuning(None, 1, 1, 2) == N.KC_EINVAL
+    assert L.kc_set_strip_waves(None, 1) == N.KC_EINVAL
+    w = ctypes.c_int32()
+    assert L.kc_get_strip_waves(None, ctypes.byref(w)) == N.KC_EINVAL
     assert L.kc_time(None, None, None) == N.KC_EINVAL
     assert L.kc_last_error(None) == b"null context"
 

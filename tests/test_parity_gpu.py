@@ -210,6 +210,13 @@ def test_error_paths():
     S.set_fields(torch.tensor(b, device="cuda"), torch.tensor(n, device="cuda"),
                  torch.tensor(s, device="cuda"))
     S.step(3)
+    # wavefronts per strip: 1 or 2 only; a depth that does not split in halves
+    # of whole steps runs one wavefront per strip with the same bits
+    for w in (0, 3, -1):
+        assert N.lib().kc_set_strip_waves(S.ctx, w) == N.KC_EINVAL
+    S.set_tuning(3, 8, 2, 2)
+    assert S.strip_waves() == 2
+    S.step(3)
     S.close()
     T = _solver(32, 32, 0.3)  # 0.3 > 1/(4 * 1) : unstable for D_n = 1
     with pytest.raises(N.KcError) as e:
