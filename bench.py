@@ -58,9 +58,10 @@ T_START = time.perf_counter()
 # published MI355X FP32 vector peak (packed FMA) and the non-packed half of it
 FP32_PEAK_TFLOPS = 157.3
 FP32_NONPACKED_TFLOPS = 78.6
-# floating-point operations per cell-update (FMA = 2): 33 VALU operations of which
-# 6 are FMAs, 2 compares, 2 selects and 1 reciprocal; counted as flops: 55 with
-# the FMAs doubled and the selects and compares included (the survey's count)
+# floating-point operations per cell-update (FMA = 2) of the textbook per-cell
+# form, which evaluates each of a cell's four face fluxes itself: coefficients 8,
+# four faces 4 x 8, two net fluxes 6, update 9 = 55.  This implementation shares
+# each face between its two cells and needs 33 VALU operations (39 flops).
 FLOPS_PER_CELL_UPDATE = 55
 METRIC = "GCell-updates/s & % HBM peak (4096^2 FP32); velocity-map pts/s at <=2% err"
 STEP_SOURCES = ("paper_1301_5058_amd/csrc/kc_step.hip", "paper_1301_5058_amd/csrc/kc_step_kernels.h",
