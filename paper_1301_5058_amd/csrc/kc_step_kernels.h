@@ -81,11 +81,13 @@ __global__ __launch_bounds__(256) void step_stream(StepArgs<R> a)
 // ring the first fills (stream_strip roles SPLIT_FIRST / SPLIT_SECOND).  Each
 // wavefront holds half the level state, so twice as many fit on a SIMD for
 // the same strips and halo; fields are the same bits as step_stream's.
-// Register budget of a split kernel: the FP32 four-level kernels with the
-// static agar field fit three wavefronts per SIMD (at most 168 VGPRs) without
-// spilling; the others keep the compiler's choice.
+// Register budget of a split kernel: the FP32 four-level kernels are held to
+// three wavefronts per SIMD (at most 168 VGPRs).  With the static agar field
+// they fit without spilling; with per-step noise the generator's state spills
+// a few dozen registers, and the third wavefront still wins (2048^2 RK2: 3 %;
+// prefetch 4 at 4096^2: 30 %).  The others keep the compiler's choice.
 template <typename R, int T, bool NOISE> struct SplitWaves {
-    static constexpr bool three = sizeof(R) == 4 && T == 4 && !NOISE;
+    static constexpr bool three = sizeof(R) == 4 && T == 4;
     static constexpr int lo = three ? 3 : 1;
     static constexpr int hi = three ? 3 : 8;
 };
