@@ -77,11 +77,29 @@ os.environ.setdefault("KC_AUTOTUNE_CACHE",
                       os.path.join(ROOT, "paper_1301_5058_amd", "tuning", "gfx950.jsonl"))
 
 
+def _code_only(text):
+    """Source text without comments and blank lines (C/C++ `//` and `/* */`
+    comments, Python `#` comments), so that editing a comment leaves the hash
+    of the kernel sources unchanged."""
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    lines = []
+    for ln in text.splitlines():
+        ln = re.sub(r"//.*$", "", ln)
+        if ln.lstrip().startswith("#") and not re.match(r"\s*#\s*(include|define|pragma|if|else|"
+                                                        r"endif|undef)", ln):
+            continue
+        if ln.strip():
+            lines.append(ln.rstrip())
+    return "\n".join(lines)
+
+
 def kernel_hash():
+    """Hash of the step kernel's sources (code only) and build flags; the PMC
+    summaries under profiles/ record the hash of the sources they measured."""
     h = hashlib.sha256()
     for rel in STEP_SOURCES:
-        with open(os.path.join(ROOT, rel), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, rel), encoding="utf-8") as f:
+            h.update(_code_only(f.read()).encode())
     return h.hexdigest()[:16]
 
 

@@ -8,8 +8,9 @@
 // level loses one valid column at either strip edge, so strips overlap by
 // HX >= T columns (a multiple of VEC) and by T rows above and below.  Input
 // rows are prefetched PF rows ahead into a register ring.  HBM traffic per
-// launch: read b, n, sigma once, write b', n' once, plus halo re-reads that
-// mostly hit L2.
+// launch: read b, n, sigma once, write b', n' once, plus the halo: the 2 T
+// rows a strip shares with its vertical neighbours are read by both, at
+// opposite ends of their walks, so L2 rarely still holds them.
 //
 // No-flux walls by reflection: cells outside the grid are ghost cells holding
 // the values of their mirror images (row -1 mirrors row 0, row -2 row 1, ...,
