@@ -69,8 +69,17 @@ STEP_SOURCES = ("paper_1301_5058_amd/csrc/kc_step.hip", "paper_1301_5058_amd/csr
                 "paper_1301_5058_amd/csrc/kc_stream_f32_euler4.hip",
                 "paper_1301_5058_amd/csrc/kc_stream.h", "paper_1301_5058_amd/csrc/kc_device.h",
                 "paper_1301_5058_amd/build.py")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_stream_4096_fp32_traffic.txt")
-COUNTERS_FILE = os.path.join(ROOT, "profiles", "step_stream_4096_fp32_counters.txt")
+# PMC summaries of the bench kernel, one pair per profiled configuration
+TRAFFIC_FILES = [os.path.join(ROOT, "profiles", f) for f in
+                 ("step_stream_4096_fp32_traffic.txt", "step_split_4096_fp32_traffic.txt")]
+COUNTERS_FILES = [os.path.join(ROOT, "profiles", f) for f in
+                  ("step_stream_4096_fp32_counters.txt", "step_split_4096_fp32_counters.txt")]
+# The two 4096^2 FP32 configurations (tsteps, rows, prefetch, wavefronts per
+# strip) that the autotuner ranks within a few per cent of each other, in an
+# order that changes from one MI355X to another: the shipped database's pick
+# (one wavefront per strip) and the split kernel's.  bench.py times both on
+# the GPU it runs on and keeps the faster; both are profiled under profiles/.
+CANDIDATES_4096 = [(4, 35, 4, 1), (4, 46, 4, 2)]
 # shipped autotune database (written by paper_1301_5058_amd/tune_db.py on an MI355X);
 # grids without an entry are timed on the spot
 os.environ.setdefault("KC_AUTOTUNE_CACHE",
@@ -108,21 +117,27 @@ def _tuning_matches(kv, tsteps, rows, prefetch, waves):
             int(kv.get("waves", 1))) == (tsteps, rows, prefetch, waves)
 
 
+def _summary(paths, tsteps, rows, prefetch, waves):
+    """(path, key-value pairs) of the PMC summary among `paths` that was taken
+    for this configuration and the current kernel sources, or None."""
+    for path in paths:
+        try:
+            txt = open(path).read()
+        except OSError:
+            continue
+        kv = dict(re.findall(r"^(\w+)\s*=\s*(\S+)", txt, flags=re.M))
+        if kv.get("kernel_sources_sha256_16") == kernel_hash() and \
+                _tuning_matches(kv, tsteps, rows, prefetch, waves):
+            return path, kv
+    return None
+
+
 def measured_traffic(tsteps, rows, prefetch, waves=1):
     """HBM bytes per step-kernel launch from the committed PMC summary, or None
-    when the summary is missing, was taken for another configuration, or for
-    older kernel sources."""
+    when no summary was taken for this configuration and these kernel sources."""
+    found = _summary(TRAFFIC_FILES, tsteps, rows, prefetch, waves)
     try:
-        txt = open(TRAFFIC_FILE).read()
-    except OSError:
-        return None
-    kv = dict(re.findall(r"^(\w+)\s*=\s*(\S+)", txt, flags=re.M))
-    if kv.get("kernel_sources_sha256_16") != kernel_hash():
-        return None
-    if not _tuning_matches(kv, tsteps, rows, prefetch, waves):
-        return None
-    try:
-        return float(kv["hbm_bytes_per_launch"])
+        return float(found[1]["hbm_bytes_per_launch"]) if found else None
     except (KeyError, ValueError):
         return None
 
@@ -130,21 +145,14 @@ def measured_traffic(tsteps, rows, prefetch, waves=1):
 def measured_counters(tsteps, rows, prefetch, waves=1):
     """VALU counters of the step kernel from the committed PMC summary (issued
     VALU instructions per useful cell-update, VALU busy fraction), or None when
-    the summary is missing or was taken for another configuration or older
-    kernel sources."""
-    try:
-        txt = open(COUNTERS_FILE).read()
-    except OSError:
-        return None
-    kv = dict(re.findall(r"^(\w+)\s*=\s*(\S+)", txt, flags=re.M))
-    if kv.get("kernel_sources_sha256_16") != kernel_hash():
-        return None
-    if not _tuning_matches(kv, tsteps, rows, prefetch, waves):
+    no summary was taken for this configuration and these kernel sources."""
+    found = _summary(COUNTERS_FILES, tsteps, rows, prefetch, waves)
+    if not found:
         return None
     try:
-        return {"valu_issued_per_update": float(kv["valu_issued_per_update"]),
-                "valu_busy": float(kv["valu_busy"]),
-                "source": os.path.relpath(COUNTERS_FILE, ROOT)}
+        return {"valu_issued_per_update": float(found[1]["valu_issued_per_update"]),
+                "valu_busy": float(found[1]["valu_busy"]),
+                "source": os.path.relpath(found[0], ROOT)}
     except (KeyError, ValueError):
         return None
 
@@ -276,6 +284,22 @@ def run(args):
     S = Solver(nx, ny, dt=dt, chi=chi, precision="fp32", b_thr=0.5 * cfg["n0"], stream=stream)
     S.set_fields(tb, tn, ts)
     tuned = S.autotune(effort=0 if args.quick_tune else 1, use_cache=True)
+    choice = None
+    if args.tuning:
+        S.set_tuning(*(int(v) for v in args.tuning.split(",")))
+    elif not args.quick_tune:
+        # the faster of the two profiled configurations on this GPU (best of
+        # two probes of 40 launches each), then the fields again from the start
+        us = [1e30] * len(CANDIDATES_4096)
+        for _ in range(2):
+            for k, cand in enumerate(CANDIDATES_4096):
+                S.set_tuning(*cand)
+                us[k] = min(us[k], launch_probe(S, stream, 40) * 1e3)
+        best = CANDIDATES_4096[us.index(min(us))]
+        S.set_tuning(*best)
+        S.set_fields(tb, tn, ts)
+        choice = {"candidates": [list(c) for c in CANDIDATES_4096],
+                  "launch_us": [round(u, 2) for u in us]}
     tsteps, rows, pf = S.tuning()
     waves = S.strip_waves()
     progress("autotuned 4096^2 fp32: T=%d rows=%d prefetch=%d waves/strip=%d (%.1f GCell/s)"
@@ -330,7 +354,8 @@ def run(args):
                                "chi=1 receptor law, forward Euler; one step = 100 time steps "
                                "+ fused diagnostics",
                    "nx": nx, "ny": ny, "dt": dt, "chi": chi, "tsteps": tsteps, "rows": rows,
-                   "prefetch": pf, "waves_per_strip": waves, "autotune_gcell_s": round(tuned, 1)},
+                   "prefetch": pf, "waves_per_strip": waves, "autotune_gcell_s": round(tuned, 1),
+                   "configuration_choice": choice},
         "roofline": main_rl,
         "effective_hbm_frac": round(value * 1e9 * 20 / (HBM_PEAK_GBS * 1e9), 4),
         "wall_s": round(wall, 3),
@@ -586,6 +611,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--quick-tune", action="store_true")
     ap.add_argument("--copy-ref-mib", type=int, default=0)
+    ap.add_argument("--tuning", default="",
+                    help="T,ROWS,PF,WAVES: run this configuration (profiling runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: the solver runs on one GPU; --gpus %d is not supported "
