@@ -221,6 +221,26 @@ def launch_probe(S, stream, launches=60):
     return e0.elapsed_time(e1) / launches
 
 
+def copy_bandwidth(mib=1024, reps=5):
+    """GB/s (bytes read + written) of a plain device-to-device copy of `mib`
+    MiB, best of `reps`, timed with HIP events: what HBM delivers to a
+    streaming kernel on this GPU."""
+    import torch
+    x = torch.ones(mib * 262144, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    best = 1e30
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        y.copy_(x)
+        e1.record()
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    del x, y
+    return 2 * mib * 1048576 / (best * 1e-3) / 1e9
+
+
 def roofline(precision, cells, tsteps, launch_ms, ops_per_update=OPS_PER_CELL_UPDATE,
              bytes_per_cell=None):
     """Roofline of the fused step kernel: the bound (HBM or VALU) with the
@@ -326,6 +346,8 @@ def run(args):
                                                  tsteps, pf)
     main_rl["launch_us"] = round(launch_ms * 1e3, 3)
     main_rl["other_bound"] = other_rl
+    # context for the HBM figures: a plain 1 GiB device-to-device copy
+    other_rl["copy_gbs"] = round(copy_bandwidth(), 1)
     # the same launch priced in flops: 55 per update against the published
     # FP32 peak (which counts packed FMAs, not used here) and its non-packed half
     tflops = FLOPS_PER_CELL_UPDATE * cells * tsteps / (launch_ms / 1e3) / 1e12
@@ -357,6 +379,8 @@ def run(args):
                    "prefetch": pf, "waves_per_strip": waves, "autotune_gcell_s": round(tuned, 1),
                    "configuration_choice": choice},
         "roofline": main_rl,
+        # 20 B per cell-update against 8 TB/s: above 1 because a launch reads
+        # and writes each cell once for 4 time steps (temporal blocking)
         "effective_hbm_frac": round(value * 1e9 * 20 / (HBM_PEAK_GBS * 1e9), 4),
         "wall_s": round(wall, 3),
         "final_diag": {"t": float(last[0]), "mass": float(last[1]), "nutrient": float(last[2]),
