@@ -86,20 +86,33 @@ os.environ.setdefault("KC_AUTOTUNE_CACHE",
                       os.path.join(ROOT, "paper_1301_5058_amd", "tuning", "gfx950.jsonl"))
 
 
-def _code_only(text):
+def _code_only(text, python=False):
     """Source text without comments and blank lines (C/C++ `//` and `/* */`
-    comments, Python `#` comments), so that editing a comment leaves the hash
-    of the kernel sources unchanged."""
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    lines = []
-    for ln in text.splitlines():
-        ln = re.sub(r"//.*$", "", ln)
-        if ln.lstrip().startswith("#") and not re.match(r"\s*#\s*(include|define|pragma|if|else|"
-                                                        r"endif|undef)", ln):
-            continue
-        if ln.strip():
-            lines.append(ln.rstrip())
-    return "\n".join(lines)
+    comments outside string literals, or Python `#` comments), so that editing
+    a comment leaves the hash of the kernel sources unchanged."""
+    out, i, n = [], 0, len(text)
+    while i < n:
+        c = text[i]
+        if c == '"' or c == "'":  # a literal, copied as it stands
+            j = i + 1
+            while j < n and text[j] != c and text[j] != "\n":
+                j += 2 if text[j] == "\\" else 1
+            out.append(text[i:j + 1])
+            i = j + 1
+        elif python and c == "#":
+            while i < n and text[i] != "\n":
+                i += 1
+        elif not python and text.startswith("//", i):
+            while i < n and text[i] != "\n":
+                i += 1
+        elif not python and text.startswith("/*", i):
+            j = text.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+        else:
+            out.append(c)
+            i += 1
+    lines = [ln.rstrip() for ln in "".join(out).splitlines()]
+    return "\n".join(ln for ln in lines if ln.strip())
 
 
 def kernel_hash():
@@ -108,7 +121,7 @@ def kernel_hash():
     h = hashlib.sha256()
     for rel in STEP_SOURCES:
         with open(os.path.join(ROOT, rel), encoding="utf-8") as f:
-            h.update(_code_only(f.read()).encode())
+            h.update(_code_only(f.read(), python=rel.endswith(".py")).encode())
     return h.hexdigest()[:16]
 
 

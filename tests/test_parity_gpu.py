@@ -322,35 +322,43 @@ def test_crop_512_long_run_matches_oracle():
 
 def test_bench_configuration_whole_field_matches_oracle():
     # the benchmark's own path: the 4096^2 FP32 workload (chi = 1) in the shipped
-    # tuning, kc_step_sample every 100 steps, 2000 steps; every cell of both
-    # fields against the FP64 oracle, and the last sample's mass and radii
+    # tuning and in the other configuration bench.py may pick on a given GPU (4
+    # steps per launch, 46-row strips, prefetch 4, two wavefronts per strip),
+    # kc_step_sample every 100 steps, 2000 steps; every cell of both fields
+    # against the FP64 oracle, and the last sample's mass and radii
     from paper_1301_5058_amd.solver import Solver
     cfg = workload.SINGLE_4096
     nx, ny = cfg["nx"], cfg["ny"]
     b, n, s = workload.fields(nx, ny, cfg["n0"], cfg["a"], cfg["seed"])
     dt = workload.config_dt(b, n, s)
-    tuning = _shipped_tuning("|4096x4096|fp32|receptor", exact=True)
-    assert tuning is not None
-    S = Solver(nx, ny, dt=dt, chi=cfg["chi"], b_thr=0.5 * cfg["n0"])
-    S.set_fields(torch.from_numpy(b).cuda(), torch.from_numpy(n).cuda(), torch.from_numpy(s).cuda())
-    S.set_tuning(*tuning)
+    shipped = _shipped_tuning("|4096x4096|fp32|receptor", exact=True)
+    assert shipped is not None
     steps, every = 2000, 100
-    series = torch.zeros((steps // every, 5), dtype=torch.float64, device="cuda")
-    for i in range(steps // every):
-        S.step_sample(every, series[i])
-    gb, gn = S.get_fields()
-    last = series[-1].cpu().numpy()
-    S.close()
     ob, on = oracle.run(b, n, s, 1.0, dt, steps, chi=cfg["chi"])
     m, nu, r, ra = oracle.diag(ob, on, 1.0, 0.5 * cfg["n0"], area=True)
-    eb, en = normwise(gb, ob), normwise(gn, on)
-    print("4096^2 x %d steps, tuning %s: normwise b %.3e n %.3e; mass %.9g (oracle %.9g), "
-          "envelope radius %.6f (%.6f), area radius %.6f (%.6f)"
-          % (steps, tuning, eb, en, last[1], m, last[3], r, last[4], ra))
-    assert last[0] == pytest.approx(steps * dt, rel=1e-15)
-    assert eb <= 1e-4 and en <= 1e-4
-    assert abs(last[1] - m) <= 5e-3 * m and abs(last[2] - nu) <= 5e-3 * nu
-    assert abs(last[3] - r) <= 5e-3 * r and abs(last[4] - ra) <= 5e-3 * ra
+    runs = []
+    for tuning in sorted({tuple(shipped), (4, 46, 4, 2)}):
+        S = Solver(nx, ny, dt=dt, chi=cfg["chi"], b_thr=0.5 * cfg["n0"])
+        S.set_fields(torch.from_numpy(b).cuda(), torch.from_numpy(n).cuda(),
+                     torch.from_numpy(s).cuda())
+        S.set_tuning(*tuning)
+        series = torch.zeros((steps // every, 5), dtype=torch.float64, device="cuda")
+        for i in range(steps // every):
+            S.step_sample(every, series[i])
+        gb, gn = S.get_fields()
+        last = series[-1].cpu().numpy()
+        S.close()
+        eb, en = normwise(gb, ob), normwise(gn, on)
+        print("4096^2 x %d steps, tuning %s: normwise b %.3e n %.3e; mass %.9g (oracle %.9g), "
+              "envelope radius %.6f (%.6f), area radius %.6f (%.6f)"
+              % (steps, tuning, eb, en, last[1], m, last[3], r, last[4], ra))
+        assert last[0] == pytest.approx(steps * dt, rel=1e-15)
+        assert eb <= 1e-4 and en <= 1e-4
+        assert abs(last[1] - m) <= 5e-3 * m and abs(last[2] - nu) <= 5e-3 * nu
+        assert abs(last[3] - r) <= 5e-3 * r and abs(last[4] - ra) <= 5e-3 * ra
+        runs.append((gb, gn))
+    # every launch shape gives the same bits
+    assert all(np.array_equal(g[0], runs[0][0]) and np.array_equal(g[1], runs[0][1]) for g in runs)
 
 
 # ----------------------------------------------------------------------------
