@@ -13,9 +13,10 @@
  *
  * The normalised system has D_n = theta = kappa = 1 and a free agar field
  * sigma = sigma0 (1 + Delta) (eq. CoefCrsDif); the three rates are kept as
- * parameters.  The paper's scheme is "explicit ... finite differences"
- * (Sec. 3).  This library advances the system with forward Euler on nx * ny
- * cell-centred finite volumes of width h: the face diffusivity of the b-flux
+ * parameters.  The paper integrates with an explicit finite-difference scheme
+ * (Sec. 3).  This library advances the system with forward Euler, or the
+ * two-stage Runge-Kutta method (KC_RK2), on nx * ny cell-centred finite
+ * volumes of width h: the face diffusivity of the b-flux
  * is the mean of sigma n b over the two cells, the chemotactic coefficient
  * sigma n b^2 chihat(n) is taken from the donor cell (the cell the nutrient
  * gradient points away from), and every boundary face carries zero flux.

@@ -4,8 +4,8 @@ For every (n0, chi0) of the experiment one 1 x cells grid on [0, length] runs
 the system velo-system-1d (constant sensitivity, sigma = sigma0): all
 instances in one batch (kb_* calls), the front position sampled on the device
 as the envelope radius about x = 0 (centre at cell index -1/2, threshold
-b_thr = min(0.5, n0 / 2): the paper's "vicinity of 0.5", below the plateau n0
-for poor nutrient), and its velocity fitted on the device over the window of
+b_thr = min(0.5, n0 / 2): Sec. 4.2 follows the point where b is about one
+half, and n0 / 2 where the plateau n0 stays below that), and its velocity fitted on the device over the window of
 front positions up to the front's own end time (its first sample past the
 window, or the time a quarter-c-bar front needs to cross it).  The velocities
 are compared with the

@@ -93,7 +93,7 @@ def sweep(count=256, meta_seed=2026, sides=(256, 512, 1024, 2048)):
 # x_i = (i + 1/2) h on [0, length]; the inoculum is cut beyond 3 r0 (r0 = 2.5),
 # as in two dimensions, because logistic growth of an uncut tail would reach
 # the threshold ahead of the front; the front is the largest x with
-# b >= min(0.5, n0 / 2) (the paper tracks a point "in the vicinity of 0.5";
+# b >= min(0.5, n0 / 2) (Sec. 4.2 follows the point where b is about one half;
 # n0 / 2 where the plateau n0 stays below it), and its speed is fitted over
 # x in [9, 17], beyond the initial support.
 # ---------------------------------------------------------------------------
