@@ -72,7 +72,7 @@ def test_noise_small_workload_fp32_matches_oracle():
     assert normwise(gb, qb) > 1e-3
 
 
-SHAPES = [(128, 128), (257, 31), (64, 1), (1, 40), (300, 97)]
+SHAPES = [(128, 128), (257, 31), (64, 1), (1, 40), (300, 97), (560, 203)]
 TUNINGS = [(1, 1, 2), (2, 7, 4), (3, 16, 2), (4, 35, 4), (8, 3, 4), (6, 1000, 2),
            (2, 7, 4, 2), (4, 35, 2, 2), (8, 3, 2, 2)]
 

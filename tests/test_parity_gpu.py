@@ -108,7 +108,8 @@ def test_one_step_elementwise(nx, ny, law):
 # ----------------------------------------------------------------------------
 # Fused launches reproduce the reference kernel bit for bit
 # ----------------------------------------------------------------------------
-SHAPES = [(128, 128), (700, 150), (257, 31), (1, 64), (64, 1), (5, 3), (300, 97)]
+# (560, 203): a last strip column of 64-80 output columns and a short last strip row
+SHAPES = [(128, 128), (700, 150), (257, 31), (1, 64), (64, 1), (5, 3), (300, 97), (560, 203)]
 # (steps per launch, rows per strip, prefetch[, wavefronts per strip])
 TUNINGS = [(1, 1, 2), (2, 7, 4), (3, 32, 2), (4, 5, 4), (6, 16, 4), (8, 3, 2), (2, 1000, 2),
            (2, 7, 4, 2), (4, 5, 2, 2), (4, 35, 4, 2), (6, 16, 2, 2), (8, 3, 4, 2), (2, 1000, 2, 2),

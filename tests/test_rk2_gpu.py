@@ -51,7 +51,7 @@ def test_rk2_differs_from_euler():
     assert normwise(r[0], ob) <= 1e-6 and normwise(r[1], on) <= 1e-6
 
 
-SHAPES = [(128, 128), (700, 150), (257, 31), (1, 64), (64, 1), (5, 3), (300, 97)]
+SHAPES = [(128, 128), (700, 150), (257, 31), (1, 64), (64, 1), (5, 3), (300, 97), (560, 203)]
 TUNINGS = [(1, 1, 2), (1, 9, 4), (2, 7, 4), (2, 35, 2), (3, 16, 4), (3, 3, 2), (4, 1000, 4),
            (2, 7, 2, 2), (2, 19, 4, 2), (2, 1000, 2, 2), (1, 5, 2, 2)]
 

@@ -45,7 +45,7 @@ CASES = [("euler", (4, 35, 4)), ("euler", (3, 7, 2)), ("euler", (8, 16, 4)), ("e
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
 @pytest.mark.parametrize("noise", [False, True])
 @pytest.mark.parametrize("integrator,tuning", CASES)
-@pytest.mark.parametrize("nx,ny", [(300, 97), (128, 128), (64, 1)])
+@pytest.mark.parametrize("nx,ny", [(300, 97), (128, 128), (64, 1), (560, 203)])
 def test_step_sample_equals_step_then_diagnostics(precision, noise, integrator, tuning, nx, ny):
     steps = 11
     A = _solver(nx, ny, precision, integrator, noise, tuning)
