@@ -93,6 +93,29 @@ def test_noise_fused_launches_bitwise_equal_to_reference(precision, nx, ny):
             assert np.array_equal(gb, rb) and np.array_equal(gn, rn), (integ, t)
 
 
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_noise_every_launch_shape_bitwise_equal_to_reference(precision):
+    # every compiled depth (Euler 1-8 steps, Runge-Kutta 1-3), short / medium /
+    # single-row-of-strips heights, both prefetch depths, one or two wavefronts
+    # per strip, on grids of odd and even width and with short last strip rows
+    import itertools
+    bad = []
+    for nx, ny in ((257, 31), (560, 203), (129, 300)):
+        b, n = _fields(nx, ny, 5)
+        rng = np.random.default_rng(nx * 3 + ny)
+        b = np.maximum(b, rng.uniform(0, 0.3, b.shape).astype(np.float32) *
+                       (rng.uniform(size=b.shape) < 0.3))
+        for integ, depths in (("euler", (1, 2, 3, 4, 6, 8)), ("rk2", (1, 2, 3))):
+            rb, rn = _run(b, n, 13, 0.08, precision=precision, ref=True, integrator=integ,
+                          chi=1.3)
+            for d, rows, pf, w in itertools.product(depths, (3, 16, 1000), (2, 4), (1, 2)):
+                gb, gn = _run(b, n, 13, 0.08, precision=precision, tuning=(d, rows, pf, w),
+                              integrator=integ, chi=1.3)
+                if not (np.array_equal(gb, rb) and np.array_equal(gn, rn)):
+                    bad.append((nx, ny, integ, d, rows, pf, w))
+    assert not bad, bad
+
+
 def test_noise_runs_split_seeded_and_resumed():
     b, n = _fields(300, 200, 2)
     dt = 0.2 / max(1.0, 0.8 * 0.7 * 1.5)  # the usual 0.2 h^2 / max(D_n, max sigma n b)
