@@ -135,6 +135,32 @@ def test_fused_launches_bitwise_equal_to_reference(precision, nx, ny):
             assert gd == rd
 
 
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_every_launch_shape_bitwise_equal_to_reference(precision):
+    # the whole product of the compiled kernels (Euler 1-8 steps and Runge-Kutta
+    # 1-3 steps per launch, both sensitivity laws, both prefetch depths, one or
+    # two wavefronts per strip) at short, medium and whole-grid strip heights, on
+    # grids of odd and even width and with short last strip rows
+    import itertools
+    bad = []
+    for nx, ny in ((257, 31), (560, 203), (129, 300)):
+        b, n, s = workload.fields(nx, ny, 0.8, 0.5, 3, r0=max(1.0, min(nx, ny) / 8.0))
+        rng = np.random.default_rng(5 * nx + ny)
+        b = np.maximum(b, rng.uniform(0, 0.3, b.shape).astype(np.float32) *
+                       (rng.uniform(size=b.shape) < 0.3))
+        for law, (integ, depths) in itertools.product(
+                ("receptor", "constant"), (("euler", (1, 2, 3, 4, 6, 8)), ("rk2", (1, 2, 3)))):
+            rb, rn, _ = run_gpu(b, n, s, 13, 0.1, precision=precision, ref=True, chi=1.7,
+                                chi_law=law, integrator=integ)
+            for d, rows, pf, w in itertools.product(depths, (3, 16, 1000), (2, 4), (1, 2)):
+                gb, gn, _ = run_gpu(b, n, s, 13, 0.1, precision=precision,
+                                    tuning=(d, rows, pf, w), chi=1.7, chi_law=law,
+                                    integrator=integ)
+                if not (np.array_equal(gb, rb) and np.array_equal(gn, rn)):
+                    bad.append((nx, ny, law, integ, d, rows, pf, w))
+    assert not bad, bad
+
+
 # ----------------------------------------------------------------------------
 # Resume, determinism, diagnostics
 # ----------------------------------------------------------------------------
