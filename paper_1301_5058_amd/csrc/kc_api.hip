@@ -226,7 +226,7 @@ int step_impl(kc_ctx *c, int64_t nsteps, double *dev_out5 = nullptr, double *ext
             if (dev_out5 && t.tsteps == nsteps) {
                 // the last launch: strip partials of the level it stores
                 nstrips = kc::stream_geom(c->p.precision, kc::stream_levels(integ, t.tsteps),
-                                          c->nx, c->ny, t.rows)
+                                          c->nx, c->ny, t.rows, 1, true)
                               .nstrips;
                 if (ext_parts) {
                     d.parts = ext_parts;
@@ -768,7 +768,7 @@ int kc_step_sample_noalloc(kc_ctx *c, int64_t nsteps, double *dev_out5)
                     "kc_step_sample_noalloc runs the fused kernel only (reference kernel selected)");
     const int d = last_launch_depth(c, nsteps);
     const int nstrips = kc::stream_geom(c->p.precision, kc::stream_levels(c->p.integrator, d),
-                                        c->nx, c->ny, c->tune.rows)
+                                        c->nx, c->ny, c->tune.rows, 1, true)
                             .nstrips;
     if (nstrips > KC_NOALLOC_MAX_STRIPS)
         return fail(c, KC_EINVAL,

@@ -51,10 +51,17 @@ int stream_levels(int integrator, int tsteps);
 // Launch geometry of the fused kernel (for the planner and the autotuner): a
 // whole-strip launch packs four strips into a workgroup, a split launch (two
 // wavefronts per strip) one strip.
+// With fold, a last strip column that holds few output columns is folded
+// (FP32 launches of at most four levels): fold_bands (>= 2) of its strips share
+// one wavefront, fold_lanes lanes each (strips [0, nmain) are the first
+// nsx_main columns row by row, the rest the folded last column); without,
+// nsx_main = nsx, nmain = nstrips, fold_bands = 1.
 struct StreamGeom {
     int nsx, nsy, nstrips, nblocks_padded, out_cols;
+    int nsx_main, nmain, fold_bands, fold_lanes;
 };
-StreamGeom stream_geom(int precision, int levels, int nx, int ny, int rows, int waves = 1);
+StreamGeom stream_geom(int precision, int levels, int nx, int ny, int rows, int waves = 1,
+                       bool fold = false);
 // Wavefronts per strip a launch of `levels` levels actually uses when `waves`
 // are asked for: 2 only where the levels split into two halves of whole time
 // steps (an even count; with Runge-Kutta an even number of steps per half).

@@ -85,7 +85,7 @@ int stream_depth_at_most(int t, int integrator)
 
 int stream_levels(int integrator, int tsteps) { return integrator == 0 ? tsteps : 2 * tsteps; }
 
-StreamGeom stream_geom(int precision, int levels, int nx, int ny, int rows, int waves)
+StreamGeom stream_geom(int precision, int levels, int nx, int ny, int rows, int waves, bool fold)
 {
     const int vec = precision == 0 ? 4 : 2;
     const int hx = (levels + vec - 1) / vec * vec;
@@ -94,6 +94,27 @@ StreamGeom stream_geom(int precision, int levels, int nx, int ny, int rows, int 
     g.nsx = (nx + g.out_cols - 1) / g.out_cols;
     g.nsy = (ny + rows - 1) / rows;
     g.nstrips = g.nsx * g.nsy;
+    g.nsx_main = g.nsx;
+    g.nmain = g.nstrips;
+    g.fold_bands = 1;
+    g.fold_lanes = 64;
+    // folding the last column (the kernels that carry the path: FP32, at most
+    // four levels): its output columns plus a halo on either side per band; the
+    // whole field addressable through one buffer resource (32-bit offsets);
+    // rows + levels <= ny keeps every row of a band's steady state below 2 ny
+    // (one reflection)
+    const int w_last = nx - (g.nsx - 1) * g.out_cols;
+    const int lanes = (2 * hx + w_last + vec - 1) / vec;
+    const int bands = 64 / lanes;
+    const double field = (double)pitch_for(nx) * ny * (precision == 0 ? 4 : 8);
+    if (fold && precision == 0 && levels <= 4 && nx % vec == 0 && bands >= 2 && g.nsy >= 2 &&
+        field < 2147483648.0 && rows + levels <= ny) {
+        g.nsx_main = g.nsx > 1 ? g.nsx - 1 : 1;
+        g.nmain = (g.nsx - 1) * g.nsy;
+        g.fold_bands = bands;
+        g.fold_lanes = lanes;
+        g.nstrips = g.nmain + (g.nsy + bands - 1) / bands;
+    }
     const int nblocks = waves == 2 ? g.nstrips : (g.nstrips + 3) / 4;
     g.nblocks_padded = (nblocks + 7) / 8 * 8;
     return g;
@@ -124,6 +145,12 @@ static StepArgs<R> make_args(const Fields<R> &f, const Coef<R> &c)
     a.pitch = f.pitch;
     a.rows = 1;
     a.nsx = a.nstrips = a.nblocks_padded = 0;
+    a.nsx_main = 1;
+    a.nmain = 0x7fffffff;
+    a.nsy = 0;
+    a.fold_bands = 1;
+    a.fold_lanes = 64;
+    a.field_bytes = 0;
     a.c = c;
     a.parts = nullptr;
     a.b_thr = a.cx = a.cy = 0.0;
@@ -156,11 +183,18 @@ hipError_t launch_stream(const Fields<R> &f, const Coef<R> &c, int chi_law, int 
     StepArgs<R> a = make_args(f, c);
     if (z)
         a.z = *z;
-    const StreamGeom g = stream_geom(sizeof(R) == 4 ? 0 : 1, levels, f.nx, f.ny, t.rows, waves);
+    const StreamGeom g =
+        stream_geom(sizeof(R) == 4 ? 0 : 1, levels, f.nx, f.ny, t.rows, waves, true);
     a.rows = t.rows;
     a.nsx = g.nsx;
     a.nstrips = g.nstrips;
     a.nblocks_padded = g.nblocks_padded;
+    a.nsx_main = g.nsx_main;
+    a.nmain = g.nmain;
+    a.nsy = g.nsy;
+    a.fold_bands = g.fold_bands;
+    a.fold_lanes = g.fold_lanes;
+    a.field_bytes = (uint32_t)((size_t)f.pitch * f.ny * sizeof(R));
     if (d) {
         a.parts = d->parts;
         a.b_thr = d->b_thr;

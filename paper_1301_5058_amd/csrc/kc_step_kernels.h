@@ -15,13 +15,27 @@ template <typename R> struct StepArgs {
     Noise<R> z;             // per-step agar noise (NOISE kernels)
     int nx, ny, pitch;
     int rows;           // output rows per strip
-    int nsx, nstrips;   // strips along x, total strips
+    int nsx, nstrips;   // strip columns, total strips
     int nblocks_padded; // grid size (multiple of 8)
+    // folded last column: strips [0, nmain) cover the first nsx_main columns
+    // row by row, strips [nmain, nstrips) the last column, fold_bands strip rows
+    // each (nsx_main = nsx and nmain = nstrips when nothing is folded)
+    int nsx_main, nmain, nsy, fold_bands, fold_lanes;
+    uint32_t field_bytes; // pitch * ny * sizeof(R) (< 2^31 when folding)
     Coef<R> c;
     // diagnostics of the stored level, or null: strip k writes {sum b, sum n,
     // max d^2 (-1: none), count of b >= b_thr} to parts[4k .. 4k + 3]
     double *parts;
     double b_thr, cx, cy;
+};
+
+// Kernels that carry the folded-strip path (stream_strip with FOLD): FP32 with
+// at most four levels.  With the path compiled into the deeper per-step-noise
+// kernels as well (FP64 with six levels, FP32 with eight), those returned
+// fields that differ from the reference kernel's, also on strips that fold
+// nothing; the cause was not found, so they are built without it.
+template <typename R, int T> struct Foldable {
+    static constexpr bool value = sizeof(R) == 4 && T <= 4;
 };
 
 // ---------------------------------------------------------------------------
@@ -51,9 +65,19 @@ __global__ __launch_bounds__(256) void step_stream(StepArgs<R> a)
     sa.b_thr = a.b_thr;
     sa.cx = a.cx;
     sa.cy = a.cy;
-    const int sx = strip % a.nsx, sy = strip / a.nsx;
+    sa.nsy = a.nsy;
+    sa.fold_bands = a.fold_bands;
+    sa.fold_lanes = a.fold_lanes;
+    sa.field_bytes = a.field_bytes;
+    constexpr bool FOLDS = Foldable<R, T>::value;
+    const bool folded = FOLDS && strip >= a.nmain;
+    const int sx = FOLDS ? (folded ? a.nsx - 1 : strip % a.nsx_main) : strip % a.nsx;
+    const int sy = FOLDS ? (folded ? strip - a.nmain : strip / a.nsx_main) : strip / a.nsx;
     constexpr int VEC = StreamShape<R>::VEC;
-    if (strip_inside<R, T>(sa, sx))
+    if (folded) {
+        if constexpr (FOLDS)
+            stream_strip<R, T, LAW, PF, true, RK, NOISE, false, WHOLE, true>(sa, sx, sy);
+    } else if (strip_inside<R, T>(sa, sx))
         stream_strip<R, T, LAW, PF, false, RK, NOISE>(sa, sx, sy);
     else if (!NOISE || a.nx % VEC == 0)
         stream_strip<R, T, LAW, PF, true, RK, NOISE>(sa, sx, sy);
@@ -63,7 +87,12 @@ __global__ __launch_bounds__(256) void step_stream(StepArgs<R> a)
         // fold the cells this strip stored into its partials (no separate pass
         // over the fields; a wave-uniform test on a kernel argument)
         DiagAcc acc{0.0, 0.0, -1.0, 0.0};
-        strip_diag<R, T>(sa, sx, sy, acc);
+        if (folded) {
+            if constexpr (FOLDS)
+                strip_diag<R, T, true>(sa, sx, sy, acc);
+        } else {
+            strip_diag<R, T>(sa, sx, sy, acc);
+        }
         const double sb = wave_sum64(acc.sb), sn = wave_sum64(acc.sn);
         const double m2 = wave_max64(acc.m2), ct = wave_sum64(acc.cnt);
         if ((threadIdx.x & 63) == 0) {
@@ -117,9 +146,25 @@ void step_split(StepArgs<R> a)
     sa.b_thr = a.b_thr;
     sa.cx = a.cx;
     sa.cy = a.cy;
-    const int sx = strip % a.nsx, sy = strip / a.nsx;
+    sa.nsy = a.nsy;
+    sa.fold_bands = a.fold_bands;
+    sa.fold_lanes = a.fold_lanes;
+    sa.field_bytes = a.field_bytes;
+    constexpr bool FOLDS = Foldable<R, T>::value;
+    const bool folded = FOLDS && strip >= a.nmain;
+    const int sx = FOLDS ? (folded ? a.nsx - 1 : strip % a.nsx_main) : strip % a.nsx;
+    const int sy = FOLDS ? (folded ? strip - a.nmain : strip / a.nsx_main) : strip / a.nsx;
     constexpr int VEC = StreamShape<R>::VEC;
-    if (strip_inside<R, T>(sa, sx)) {
+    if (folded) {
+        if constexpr (FOLDS) {
+            if (second)
+                stream_strip<R, T, LAW, PF, true, RK, NOISE, false, SPLIT_SECOND, true>(
+                    sa, sx, sy, &ring);
+            else
+                stream_strip<R, T, LAW, PF, true, RK, NOISE, false, SPLIT_FIRST, true>(
+                    sa, sx, sy, &ring);
+        }
+    } else if (strip_inside<R, T>(sa, sx)) {
         if (second)
             stream_strip<R, T, LAW, PF, false, RK, NOISE, false, SPLIT_SECOND>(sa, sx, sy, &ring);
         else
@@ -137,7 +182,12 @@ void step_split(StepArgs<R> a)
     }
     if (second && a.parts) {
         DiagAcc acc{0.0, 0.0, -1.0, 0.0};
-        strip_diag<R, T>(sa, sx, sy, acc);
+        if (folded) {
+            if constexpr (FOLDS)
+                strip_diag<R, T, true>(sa, sx, sy, acc);
+        } else {
+            strip_diag<R, T>(sa, sx, sy, acc);
+        }
         const double sb = wave_sum64(acc.sb), sn = wave_sum64(acc.sn);
         const double m2 = wave_max64(acc.m2), ct = wave_sum64(acc.cnt);
         if ((threadIdx.x & 63) == 0) {

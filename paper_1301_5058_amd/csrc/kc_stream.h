@@ -44,6 +44,16 @@
 // on which every level is active (the steady state between the first T - 1 + T
 // and the last rows) runs a straight-line body without it.
 //
+// A folded strip (FOLD) serves the last strip column of a grid whose last
+// column holds few output cells: its wavefront holds several bands of
+// fold_lanes lanes, band j advancing the strip of row sy * fold_bands + j of
+// that column (each band a narrow strip with its own halo lanes; what the DPP
+// exchange brings in across a band boundary stays in the halo).  The walk runs
+// in coordinates relative to each band's first output row, so the loops and
+// the level tests stay wave-uniform; rows in memory are per lane.  The last
+// strip row may be short: its band computes the nominal rows (ghost rows below
+// the grid, mirrored like any) and stores only those inside.
+//
 // strip_diag reads back the cells a strip has just stored (each lane its own
 // addresses, so program order makes the stores visible) and folds them into a
 // per-lane accumulator: sum b, sum n in double, the largest squared distance
@@ -74,6 +84,9 @@ template <typename R> struct StripArgs {
     R *b_out, *n_out;
     int nx, ny, pitch;
     int rows; // output rows per strip
+    int nsy;  // strip rows (FOLD only)
+    int fold_bands, fold_lanes; // bands of a folded strip and lanes per band (FOLD only)
+    uint32_t field_bytes;       // bytes of one field, pitch * ny (FOLD only)
     Coef<R> c;
     Noise<R> z;           // per-step agar noise (NOISE only; sg unused then)
     double b_thr, cx, cy; // envelope diagnostics (strip_diag only)
@@ -171,10 +184,12 @@ template <typename R, int PF> struct SplitRing {
 };
 
 template <typename R, int T, int LAW, int PF, bool EDGE, bool RK = false, bool NOISE = false,
-          bool GEN = false, int ROLE = WHOLE>
+          bool GEN = false, int ROLE = WHOLE, bool FOLD = false>
 __device__ __forceinline__ void stream_strip(const StripArgs<R> &a, int sx, int sy,
                                              SplitRing<R, PF> *ring = nullptr)
 {
+    static_assert(!FOLD || (EDGE && !GEN), "a folded strip is an edge strip of a grid whose "
+                                           "width is a multiple of the vector width");
     static_assert(!RK || T % 2 == 0, "a two-stage Runge-Kutta block has an even level count");
     static_assert(ROLE == WHOLE || (T % 2 == 0 && (!RK || (T / 2) % 2 == 0)),
                   "a split strip hands over whole time steps");
@@ -187,12 +202,27 @@ __device__ __forceinline__ void stream_strip(const StripArgs<R> &a, int sx, int 
     typedef typename VecT<R, VEC>::type vec_t;
 
     const int lane = threadIdx.x & 63;
-    const int x0 = sx * OW - HX + lane * VEC; // first column of this lane
-    const int y0 = sy * a.rows;
-    const int y1 = min(y0 + a.rows, a.ny);
+    // FOLD: the lane's band and its lane within the band; a lane past the last
+    // band (or whose strip row does not exist) follows band 0 and stores nothing
+    int lb = lane, sy_l = sy;
+    bool band_ok = true;
+    if constexpr (FOLD) {
+        const int band = lane / a.fold_lanes;
+        lb = lane - band * a.fold_lanes;
+        band_ok = band < a.fold_bands && sy * a.fold_bands + band < a.nsy;
+        sy_l = sy * a.fold_bands + (band_ok ? band : 0);
+    }
+    const int x0 = sx * OW - HX + lb * VEC; // first column of this lane
+    // rows: absolute (y0 = first output row), or with FOLD relative to the
+    // lane's band (ybase its first output row, ylim one past its last in the grid)
+    const int ybase = FOLD ? sy_l * a.rows : 0;
+    const int ylim = FOLD ? min(ybase + a.rows, a.ny) : 0;
+    const int y0 = FOLD ? 0 : sy * a.rows;
+    const int y1 = FOLD ? a.rows : min(y0 + a.rows, a.ny);
     const int rs = y0 - T; // first input row (rows outside the grid are mirrored)
     const int re = y1 + T; // one past the last input row needed
-    const bool lane_out = (lane * VEC >= HX) && (lane * VEC < WC - HX) && (x0 < a.nx);
+    const bool lane_out =
+        band_ok && (lb * VEC >= HX) && (lb * VEC < WC - HX) && (x0 < a.nx);
 
     // Edge strips: the mirrored column of each of the lane's cells.  When nx is
     // a multiple of VEC (GEN = false) the reflections map every aligned block of
@@ -228,13 +258,29 @@ __device__ __forceinline__ void stream_strip(const StripArgs<R> &a, int sx, int 
     // general.
     vec_t pb[PF], pn[PF], ps[PF];
     auto mrow = [&](int row, auto full_tag) __attribute__((always_inline)) {
+        const int r = FOLD ? ybase + row : row;
         if constexpr (decltype(full_tag)::value)
-            return mirror_high(row, a.ny);
+            return mirror_high(r, a.ny);
         else
-            return mirror_index(row, a.ny);
+            return mirror_index(r, a.ny);
     };
     auto load_row = [&](int row, vec_t &vb, vec_t &vn, vec_t &vs, auto full_tag)
                         __attribute__((always_inline)) {
+        if constexpr (FOLD) {
+            // the row differs per lane: the whole field through one buffer
+            // resource, row and column in the lane's byte offset
+            const uint32_t rowoff = (uint32_t)mrow(row, full_tag) * (uint32_t)a.pitch;
+            const __amdgpu_buffer_rsrc_t rb = row_rsrc(a.b_in, (int)a.field_bytes);
+            const __amdgpu_buffer_rsrc_t rn = row_rsrc(a.n_in, (int)a.field_bytes);
+#pragma unroll
+            for (int k = 0; k < VEC; ++k) {
+                const uint32_t o = (rowoff + (uint32_t)xm[k]) * (uint32_t)sizeof(R);
+                vb[k] = buf_load<R>(rb, o);
+                vn[k] = buf_load<R>(rn, o);
+                vs[k] = NOISE ? R(0) : buf_load<R>(row_rsrc(a.sg, (int)a.field_bytes), o);
+            }
+            return;
+        }
         // the row (uniform) through a buffer resource, the lane's byte offset
         const size_t base = (size_t)mrow(row, full_tag) * a.pitch;
         const int nbytes = a.pitch * (int)sizeof(R);
@@ -283,7 +329,13 @@ __device__ __forceinline__ void stream_strip(const StripArgs<R> &a, int sx, int 
     // the second wavefront of a split strip loads only sigma (static field),
     // for its incoming rows (row - L0 at iteration row)
     auto load_sigma = [&](int row, vec_t &vs, auto full_tag) __attribute__((always_inline)) {
-        if constexpr (!NOISE) {
+        if constexpr (!NOISE && FOLD) {
+            const uint32_t rowoff = (uint32_t)mrow(row, full_tag) * (uint32_t)a.pitch;
+            const __amdgpu_buffer_rsrc_t rsg = row_rsrc(a.sg, (int)a.field_bytes);
+#pragma unroll
+            for (int k = 0; k < VEC; ++k)
+                vs[k] = buf_load<R>(rsg, (rowoff + (uint32_t)xm[k]) * (uint32_t)sizeof(R));
+        } else if constexpr (!NOISE) {
             const size_t base = (size_t)mrow(row, full_tag) * a.pitch;
             const int nbytes = a.pitch * (int)sizeof(R);
             const __amdgpu_buffer_rsrc_t rsg = row_rsrc(a.sg + base, nbytes);
@@ -441,18 +493,26 @@ __device__ __forceinline__ void stream_strip(const StripArgs<R> &a, int sx, int 
                         ib[k] = ob[k];
                         in[k] = on[k];
                     }
-                } else if (y >= y0 && y < y1 && lane_out) {
+                } else if (y >= y0 && y < y1 && lane_out && (!FOLD || ybase + y < ylim)) {
                     vec_t vb, vn;
 #pragma unroll
                     for (int k = 0; k < VEC; ++k) {
                         vb[k] = ob[k];
                         vn[k] = on[k];
                     }
-                    const size_t rowp = (size_t)y * a.pitch;
-                    const int nbytes = a.pitch * (int)sizeof(R);
-                    const uint32_t o = (uint32_t)x0 * (uint32_t)sizeof(R);
-                    buf_store16<vec_t>(vb, row_rsrc(a.b_out + rowp, nbytes), o);
-                    buf_store16<vec_t>(vn, row_rsrc(a.n_out + rowp, nbytes), o);
+                    if constexpr (FOLD) {
+                        const uint32_t o =
+                            ((uint32_t)(ybase + y) * (uint32_t)a.pitch + (uint32_t)x0) *
+                            (uint32_t)sizeof(R);
+                        buf_store16<vec_t>(vb, row_rsrc(a.b_out, (int)a.field_bytes), o);
+                        buf_store16<vec_t>(vn, row_rsrc(a.n_out, (int)a.field_bytes), o);
+                    } else {
+                        const size_t rowp = (size_t)y * a.pitch;
+                        const int nbytes = a.pitch * (int)sizeof(R);
+                        const uint32_t o = (uint32_t)x0 * (uint32_t)sizeof(R);
+                        buf_store16<vec_t>(vb, row_rsrc(a.b_out + rowp, nbytes), o);
+                        buf_store16<vec_t>(vn, row_rsrc(a.n_out + rowp, nbytes), o);
+                    }
                 }
             }
             if constexpr (ROLE == SPLIT_FIRST) {
@@ -530,8 +590,9 @@ __device__ __forceinline__ void stream_strip(const StripArgs<R> &a, int sx, int 
 }
 
 // Diagnostics of the output block of strip (sx, sy) after stream_strip<.., T, ..>
-// stored it (see the header comment).
-template <typename R, int T>
+// stored it (see the header comment); FOLD: of every band of a folded strip,
+// each lane its own band's rows.
+template <typename R, int T, bool FOLD = false>
 __device__ __forceinline__ void strip_diag(const StripArgs<R> &a, int sx, int sy, DiagAcc &acc)
 {
     constexpr int VEC = StreamShape<R>::VEC;
@@ -540,10 +601,19 @@ __device__ __forceinline__ void strip_diag(const StripArgs<R> &a, int sx, int sy
     constexpr int OW = Halo<T, VEC>::OW;
     typedef typename VecT<R, VEC>::type vec_t;
     const int lane = threadIdx.x & 63;
-    const int x0 = sx * OW - HX + lane * VEC;
-    const int y0 = sy * a.rows;
+    int lb = lane, sy_l = sy;
+    bool band_ok = true;
+    if constexpr (FOLD) {
+        const int band = lane / a.fold_lanes;
+        lb = lane - band * a.fold_lanes;
+        band_ok = band < a.fold_bands && sy * a.fold_bands + band < a.nsy;
+        sy_l = sy * a.fold_bands + (band_ok ? band : 0);
+    }
+    const int x0 = sx * OW - HX + lb * VEC;
+    const int y0 = sy_l * a.rows;
     const int y1 = min(y0 + a.rows, a.ny);
-    const bool lane_out = (lane * VEC >= HX) && (lane * VEC < WC - HX) && (x0 < a.nx);
+    const bool lane_out =
+        band_ok && (lb * VEC >= HX) && (lb * VEC < WC - HX) && (x0 < a.nx);
     if (!lane_out)
         return;
     for (int y = y0; y < y1; ++y) {
