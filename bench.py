@@ -483,7 +483,7 @@ def hires(steps):
 
 
 def sweep(steps=30000, every=100):
-    """The 256-instance parameter sweep in one persistent launch."""
+    """The 256-instance parameter sweep, in the batch's tuned launch mode."""
     import numpy as np
     import torch
     from paper_1301_5058_amd import workload
