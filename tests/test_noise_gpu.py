@@ -116,6 +116,25 @@ def test_noise_every_launch_shape_bitwise_equal_to_reference(precision):
     assert not bad, bad
 
 
+def test_noise_folded_last_column_bitwise_equal_to_reference():
+    # grids whose last strip column folds (FP32 launches of up to four levels)
+    import itertools
+    from test_parity_gpu import FOLD_SHAPES
+    bad = []
+    for nx, ny in FOLD_SHAPES:
+        b, n = _fields(nx, ny, 7)
+        rng = np.random.default_rng(nx + ny)
+        b = np.maximum(b, rng.uniform(0, 0.3, b.shape).astype(np.float32) *
+                       (rng.uniform(size=b.shape) < 0.3))
+        for integ, depths in (("euler", (1, 2, 3, 4)), ("rk2", (1, 2))):
+            rb, rn = _run(b, n, 9, 0.08, ref=True, integrator=integ, chi=1.3)
+            for d, rows, pf, w in itertools.product(depths, (3, 5, 12, 40), (2, 4), (1, 2)):
+                gb, gn = _run(b, n, 9, 0.08, tuning=(d, rows, pf, w), integrator=integ, chi=1.3)
+                if not (np.array_equal(gb, rb) and np.array_equal(gn, rn)):
+                    bad.append((nx, ny, integ, d, rows, pf, w))
+    assert not bad, bad
+
+
 def test_noise_runs_split_seeded_and_resumed():
     b, n = _fields(300, 200, 2)
     dt = 0.2 / max(1.0, 0.8 * 0.7 * 1.5)  # the usual 0.2 h^2 / max(D_n, max sigma n b)

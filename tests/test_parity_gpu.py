@@ -161,6 +161,31 @@ def test_every_launch_shape_bitwise_equal_to_reference(precision):
     assert not bad, bad
 
 
+# Grids whose last strip column holds few output columns: FP32 launches of up to
+# four levels fold its strips into bands of one wavefront (4 to 16 bands here).
+FOLD_SHAPES = [(1000, 77), (520, 130), (760, 45), (1016, 33)]
+
+
+def test_folded_last_column_bitwise_equal_to_reference():
+    import itertools
+    bad = []
+    for nx, ny in FOLD_SHAPES:
+        b, n, s = workload.fields(nx, ny, 0.8, 0.5, 11, r0=max(1.0, min(nx, ny) / 8.0))
+        rng = np.random.default_rng(nx + ny)
+        b = np.maximum(b, rng.uniform(0, 0.3, b.shape).astype(np.float32) *
+                       (rng.uniform(size=b.shape) < 0.3))
+        for law, (integ, depths) in itertools.product(
+                ("receptor", "constant"), (("euler", (1, 2, 3, 4)), ("rk2", (1, 2)))):
+            rb, rn, rd = run_gpu(b, n, s, 9, 0.1, ref=True, chi=1.7, chi_law=law,
+                                 integrator=integ)
+            for d, rows, pf, w in itertools.product(depths, (3, 5, 12, 40), (2, 4), (1, 2)):
+                gb, gn, gd = run_gpu(b, n, s, 9, 0.1, tuning=(d, rows, pf, w), chi=1.7,
+                                     chi_law=law, integrator=integ)
+                if not (np.array_equal(gb, rb) and np.array_equal(gn, rn) and gd == rd):
+                    bad.append((nx, ny, law, integ, d, rows, pf, w))
+    assert not bad, bad
+
+
 # ----------------------------------------------------------------------------
 # Resume, determinism, diagnostics
 # ----------------------------------------------------------------------------
