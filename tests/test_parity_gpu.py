@@ -162,7 +162,7 @@ def test_every_launch_shape_bitwise_equal_to_reference(precision):
 
 
 # Grids whose last strip column holds few output columns: FP32 launches of up to
-# four levels fold its strips into bands of one wavefront (4 to 16 bands here).
+# four levels fold its strips into bands of one wavefront (8 to 16 bands here).
 FOLD_SHAPES = [(1000, 77), (520, 130), (760, 45), (1016, 33)]
 
 
